@@ -1,0 +1,197 @@
+/*
+ * gnmppi.h -- C ABI of the Gauss-Newton accelerated MPPI hot path
+ * (Homburger, Baumgaertner, Diehl, Reuter, arXiv 2512.04579) on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The library solves the direct single-shooting optimal control problem of
+ * Sec. 2: an initial state x0 in R^nx, a control sequence
+ * U = [u_0; ...; u_{N-1}] in R^{N nu} stacked time-major, the simulator
+ * X = F(x0, U) of Eq. (1), and a cost with the least-squares structure
+ * C = Phi(R(x0, U)) of Eq. (4) with Phi(R) = 1/2 ||R||^2.
+ *
+ * Residual convention: for each step k = 0..N-1 the residual holds nx rows
+ * sqrt(2 q) .* (x_{k+1} - x_ref) followed by nu rows sqrt(2 r) .* u_k, so
+ * m = N (nx + nu) rows, n = N nu decision variables, and 1/2 ||R||^2 is the
+ * quadratic stage-plus-terminal cost of Eq. (2) (terminal weight Q, the
+ * constant x_0 term dropped).
+ *
+ * Conventions shared by every call:
+ *  - All array pointers are DEVICE pointers owned by the caller; the library
+ *    never allocates or frees memory and keeps no state between calls.
+ *  - Element type is uniform per call: GNMPPI_F32 (float) or GNMPPI_F64
+ *    (double).  Normal-equation factorisations run in double regardless.
+ *  - Matrices over samples are "sample-fastest": element (row i, sample s)
+ *    of a matrix with leading dimension ld sits at index i*ld + s.
+ *  - Every call only enqueues work on `stream` (a hipStream_t; NULL is the
+ *    null stream) and returns without synchronising, so a sequence of calls
+ *    can be captured into a HIP graph.  The calls do not issue memsets.
+ *  - Host-detectable errors (NULL required pointer, non-positive or
+ *    inconsistent size, too small a workspace) return a negative code
+ *    synchronously and enqueue nothing.  Numerical failures found on the
+ *    device are written to the caller's `int32_t *status` word (0 = ok), which
+ *    keeps the calls asynchronous.
+ *  - Calls on one stream are ordered; concurrent calls on different streams
+ *    must not share output or workspace buffers.
+ */
+#ifndef GNMPPI_H
+#define GNMPPI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define GNMPPI_OK          0
+#define GNMPPI_EINVAL     (-1) /* invalid argument (host, synchronous)            */
+#define GNMPPI_EHIP       (-2) /* HIP runtime error at launch (host, synchronous) */
+#define GNMPPI_ENOTPD     (-3) /* device: normal matrix J^T J + lambda I not PD    */
+#define GNMPPI_ERANK      (-4) /* device: perturbations do not span R^n (LS form)  */
+#define GNMPPI_ENONFINITE (-5) /* device: no sample / candidate had a finite cost  */
+#define GNMPPI_ENOSPACE   (-6) /* workspace smaller than the *_workspace() size    */
+
+/* ---- element types, models, estimators ---------------------------------- */
+#define GNMPPI_F32 0
+#define GNMPPI_F64 1
+
+/* Problem IV (Sec. 5): d independent double integrators with exact zero-order
+ * hold, p+ = p + dt v + dt^2/2 u, v+ = v + dt u; state (p_1..p_d, v_1..v_d),
+ * nx = 2d, nu = d, 1 <= d <= 4. */
+#define GNMPPI_MODEL_DOUBLE_INTEGRATOR 1
+/* Planar chain of M point masses (1 <= M <= 16) joined to a fixed anchor and
+ * to each other by zero-rest-length springs with force
+ * (k_lin + k_cub |d|^2) d; free masses accelerate by (T_{i+1} - T_i) / mass;
+ * the end mass moves with the commanded velocity u (nu = 2) and its velocity
+ * slot is set to u after each step; classical RK4 with u held over the step
+ * (the discretisation of Problem V).  State (p_1..p_M, v_1..v_M), each a 2-D
+ * vector, nx = 4M. */
+#define GNMPPI_MODEL_CHAIN 2
+
+/* Jacobian estimators for Eq. (10) (Sec. 4.1).
+ * LS: J = (dR W^T)(W W^T)^{-1}, the least-squares fit of the residual
+ *     differences dR = R(U + W_s) - R(U) to the perturbations; this is
+ *     Eq. (10) with Sigma replaced by the samples' second moment.
+ * MC: J = (dR W^T) / (K sigma2), the Monte-Carlo mean of Eq. (10) itself. */
+#define GNMPPI_JAC_LS 0
+#define GNMPPI_JAC_MC 1
+
+/* Problem data (Sec. 2).  Vectors are device arrays of the problem's dtype. */
+typedef struct gnmppi_problem {
+  int32_t model;    /* GNMPPI_MODEL_*                                   */
+  int32_t dtype;    /* GNMPPI_F32 or GNMPPI_F64                          */
+  int32_t nx;       /* state dimension                                   */
+  int32_t nu;       /* input dimension                                   */
+  int32_t N;        /* horizon (number of steps), >= 1                   */
+  int32_t n_masses; /* chain only: M                                     */
+  double dt;        /* step length                                       */
+  double k_lin;     /* chain only: linear spring constant                */
+  double k_cub;     /* chain only: cubic spring constant                 */
+  double mass;      /* chain only: mass of each free point mass (> 0)    */
+  const void *q;    /* nx entries: diagonal of the state weight Q (>= 0) */
+  const void *r;    /* nu entries: diagonal of the input weight R (>= 0) */
+  const void *x_ref;/* nx entries: tracking target                       */
+} gnmppi_problem;
+
+/* ---- a1: perturbation sampler (Sec. 3, W ~ N(0, sigma^2 I); antithetic
+ *      pairs as used for Methods C and D, Sec. 5) -------------------------
+ * Fills W (n x K, leading dimension ldw >= K) with sigma * z, z standard
+ * normal.  z comes from Philox4x32-10 (Salmon et al., SC'11) with
+ * key = (seed low word, seed high word) and
+ * counter = (column s, row block b, stream low word, stream high word),
+ * followed by Box-Muller:
+ *   F32: block b -> rows 4b..4b+3; words (x0,x1) give rows 4b, 4b+1 and
+ *        (x2,x3) rows 4b+2, 4b+3, with u1 = ((x>>8)+1) 2^-24 from the first
+ *        word and u2 = (x>>8) 2^-24 from the second;
+ *   F64: block b -> rows 2b, 2b+1 with u1 = (((x0<<21)|(x1>>11))+1) 2^-53
+ *        and u2 = ((x2<<21)|(x3>>11)) 2^-53;
+ *   z = sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2).
+ * With antithetic != 0, K must be even, columns s < K/2 are drawn and
+ * column s + K/2 is the exact negation of column s.  `stream_id` selects an
+ * independent sequence (e.g. the iteration number).
+ * Returns GNMPPI_EINVAL for n < 1, K < 1, ldw < K, odd K with antithetic. */
+int gnmppi_sample(int32_t dtype, int32_t n, int32_t K, double sigma,
+                  uint64_t seed, uint64_t stream_id, int32_t antithetic,
+                  void *W, int64_t ldw, void *stream);
+
+/* Method E (Sec. 5): the deterministic Dirac-mixture (sigma-point) set
+ * W = [ +sqrt(n) sigma I, -sqrt(n) sigma I ] with K = 2n columns, whose
+ * second moment is exactly sigma^2 I.  ldw >= 2n. */
+int gnmppi_sigma_points(int32_t dtype, int32_t n, double sigma, void *W,
+                        int64_t ldw, void *stream);
+
+/* ---- a2: rollout, residual and cost (Eqs. (1), (2), (4)) ----------------
+ * Single shooting of K perturbed control sequences: column s = 0..K-1 uses
+ * U + W[:, s] (W == NULL: every column uses U).  Writes the residual column
+ * s to R[i*ldr + s] (i < m; R == NULL skips it: costs only) and
+ * C[s] = 1/2 ||R[:, s]||^2.  If c0 != NULL the nominal sequence U itself is
+ * rolled out in the same launch: its cost goes to c0[0] and, if r0 != NULL,
+ * its residual to r0[0..m-1] (contiguous).  K may be 0 when c0 != NULL.
+ * x0: nx entries; U: n entries.  Errors: EINVAL for an unsupported model or
+ * size, ldw < K, ldr < K. */
+int gnmppi_rollout(const gnmppi_problem *p, const void *x0, const void *U,
+                   const void *W, int64_t ldw, int32_t K,
+                   void *R, int64_t ldr, void *C,
+                   void *r0, void *c0, void *stream);
+
+/* ---- a3: MPPI update (Eqs. (7), (8)) ------------------------------------
+ * U <- U + sum_s w_s W[:, s] / sum_s w_s with w_s = exp(-(C_s - min C)/temperature).
+ * The shift by min C cancels in the ratio.  Samples with a NaN or infinite
+ * cost get weight 0.  If no cost is finite, U is left unchanged and
+ * *status = GNMPPI_ENONFINITE, else *status = 0 (status may be NULL).
+ * weights (optional, K entries) receives the normalised w_s.  K <= 32768
+ * (F32) or 16384 (F64); temperature > 0. */
+int gnmppi_mppi_update(int32_t dtype, int32_t n, int32_t K, const void *C,
+                       const void *W, int64_t ldw, double temperature,
+                       void *U, void *weights, int32_t *status, void *stream);
+
+/* ---- a4: Jacobian reconstruction (Eq. (10), Sec. 4.1) -------------------
+ * R: m x K residuals of the perturbed columns (leading dimension ldr),
+ * r0: m nominal residuals, W: n x K perturbations (ldw).  Forms
+ * S = (R - r0 1^T) W^T and, for LS, G = W W^T, factors G in double precision
+ * and writes J = S G^{-1} (LS) or J = S / (K sigma2) (MC) as an m x n
+ * row-major matrix with leading dimension ldj >= n.  For LS, a pivot of G
+ * below n * 2^-52 * max diag(G) sets *status = GNMPPI_ERANK and J is left
+ * unspecified.  Limits: 1 <= n <= 192.  `work` is device scratch of at least
+ * gnmppi_jacobian_workspace(...) bytes, 256-byte aligned. */
+size_t gnmppi_jacobian_workspace(int32_t dtype, int32_t m, int32_t n, int32_t K);
+int gnmppi_reconstruct_jacobian(int32_t dtype, int32_t m, int32_t n, int32_t K,
+                                const void *R, int64_t ldr, const void *r0,
+                                const void *W, int64_t ldw, int32_t method,
+                                double sigma2, void *J, int64_t ldj,
+                                void *work, size_t work_bytes,
+                                int32_t *status, void *stream);
+
+/* ---- a5: Generalized Gauss-Newton step (Eq. (13), Sec. 4.2) -------------
+ * dU = -(J^T J + lm_lambda I)^{-1} J^T r0 for Phi = 1/2 ||.||^2, i.e. the
+ * minimiser of the GGN subproblem.  J: m x n row-major (ldj), r0: m entries
+ * with stride inc_r0.  J^T J and J^T r0 are accumulated and factored by
+ * Cholesky in double precision; dU is written in dtype.  A non-positive
+ * pivot sets *status = GNMPPI_ENOTPD and dU = 0.  1 <= n <= 192.
+ * `work`: at least gnmppi_ggn_workspace(...) bytes, 256-byte aligned. */
+size_t gnmppi_ggn_workspace(int32_t dtype, int32_t m, int32_t n);
+int gnmppi_ggn_step(int32_t dtype, int32_t m, int32_t n, const void *J,
+                    int64_t ldj, const void *r0, int64_t inc_r0,
+                    double lm_lambda, void *dU, void *work, size_t work_bytes,
+                    int32_t *status, void *stream);
+
+/* ---- a6: parallel line search and update (Eqs. (14), (15); Alg. 1) ------
+ * Rolls out the L candidates U + alpha[j] dU in one launch (costs only),
+ * picks j* = the first index of the smallest finite cost, and applies
+ * U <- U + alpha[j*] dU in place.  alpha: L step lengths (device, dtype),
+ * 1 <= L <= 64.  C (optional): the L candidate costs.  info (optional,
+ * device double[3]): {alpha[j*], C_j*, j*}; if no candidate cost is finite,
+ * U is unchanged and info = {0, NaN, -1}. */
+int gnmppi_line_search(const gnmppi_problem *p, const void *x0, void *U,
+                       const void *dU, const void *alpha, int32_t L, void *C,
+                       double *info, void *stream);
+
+/* ---- misc ----------------------------------------------------------------- */
+const char *gnmppi_status_string(int32_t status);
+int32_t gnmppi_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GNMPPI_H */

@@ -1,0 +1,195 @@
+"""ctypes binding of libgnmppi.so (declared in include/gnmppi.h).
+
+Argument marshalling only: every function forwards device pointers, sizes
+and the current torch stream to the C entry point of the same name, and
+raises ``GnmppiError`` on a non-zero return.  There is no fallback: if the
+shared library is missing the import of the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import c_double, c_int32, c_int64, c_size_t, c_uint64, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgnmppi.so")
+
+F32, F64 = 0, 1
+MODEL_DOUBLE_INTEGRATOR, MODEL_CHAIN = 1, 2
+JAC_LS, JAC_MC = 0, 1
+OK, EINVAL, EHIP, ENOTPD, ERANK, ENONFINITE, ENOSPACE = 0, -1, -2, -3, -4, -5, -6
+
+
+class GnmppiError(RuntimeError):
+    def __init__(self, func: str, code: int, message: str):
+        super().__init__(f"{func} returned {code}: {message}")
+        self.code = code
+
+
+class GnmppiProblem(ctypes.Structure):
+    """Mirror of ``gnmppi_problem``."""
+
+    _fields_ = [
+        ("model", c_int32), ("dtype", c_int32), ("nx", c_int32), ("nu", c_int32),
+        ("N", c_int32), ("n_masses", c_int32),
+        ("dt", c_double), ("k_lin", c_double), ("k_cub", c_double), ("mass", c_double),
+        ("q", c_void_p), ("r", c_void_p), ("x_ref", c_void_p),
+    ]
+
+
+PROBLEM_P = ctypes.POINTER(GnmppiProblem)
+I32_P = ctypes.POINTER(c_int32)
+F64_P = ctypes.POINTER(c_double)
+
+SIGNATURES = {
+    "gnmppi_sample": (c_int32, [c_int32, c_int32, c_int32, c_double, c_uint64, c_uint64, c_int32,
+                                c_void_p, c_int64, c_void_p]),
+    "gnmppi_sigma_points": (c_int32, [c_int32, c_int32, c_double, c_void_p, c_int64, c_void_p]),
+    "gnmppi_rollout": (c_int32, [PROBLEM_P, c_void_p, c_void_p, c_void_p, c_int64, c_int32,
+                                 c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "gnmppi_mppi_update": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_int64,
+                                     c_double, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "gnmppi_jacobian_workspace": (c_size_t, [c_int32, c_int32, c_int32, c_int32]),
+    "gnmppi_reconstruct_jacobian": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p,
+                                              c_int64, c_void_p, c_void_p, c_int64, c_int32,
+                                              c_double, c_void_p, c_int64, c_void_p, c_size_t,
+                                              c_void_p, c_void_p]),
+    "gnmppi_ggn_workspace": (c_size_t, [c_int32, c_int32, c_int32]),
+    "gnmppi_ggn_step": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_int64, c_void_p, c_int64,
+                                  c_double, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
+    "gnmppi_line_search": (c_int32, [PROBLEM_P, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
+                                     c_void_p, c_void_p, c_void_p]),
+    "gnmppi_status_string": (ctypes.c_char_p, [c_int32]),
+    "gnmppi_abi_version": (c_int32, []),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the shared library (once) and declare every signature."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"{path} is missing: build it first (python -m paper_2512_04579_amd.build)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_string(code: int) -> str:
+    return load().gnmppi_status_string(int(code)).decode()
+
+
+def _check(name: str, code: int):
+    if code != OK:
+        raise GnmppiError(name, code, status_string(code))
+
+
+# ---------------------------------------------------------------------------
+# tensor marshalling helpers
+# ---------------------------------------------------------------------------
+
+def _ptr(t):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+def _ld(t, default: int = 0) -> int:
+    if t is None:
+        return default
+    if t.dim() == 1:
+        return t.numel()
+    if t.stride(1) != 1:
+        raise ValueError("matrices must be row-major with unit column stride")
+    return t.stride(0)
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return c_void_p(s.cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# entry points (same names and argument order as the C ABI)
+# ---------------------------------------------------------------------------
+
+def gnmppi_sample(W, sigma: float, seed: int, stream_id: int, antithetic: bool = True,
+                  K: int | None = None, stream=None):
+    n = W.shape[0]
+    K = W.shape[1] if K is None else K
+    _check("gnmppi_sample", load().gnmppi_sample(
+        _dtype_code(W), n, K, float(sigma), int(seed) & (2 ** 64 - 1),
+        int(stream_id) & (2 ** 64 - 1), int(bool(antithetic)), _ptr(W), _ld(W), _stream(stream)))
+
+
+def gnmppi_sigma_points(W, sigma: float, stream=None):
+    n = W.shape[0]
+    _check("gnmppi_sigma_points", load().gnmppi_sigma_points(
+        _dtype_code(W), n, float(sigma), _ptr(W), _ld(W), _stream(stream)))
+
+
+def gnmppi_rollout(problem, x0, U, W, K: int, R=None, C=None, r0=None, c0=None, stream=None):
+    """``problem`` is a ``DeviceProblem`` (see ``problem.py``)."""
+    _check("gnmppi_rollout", load().gnmppi_rollout(
+        ctypes.byref(problem.c), _ptr(x0), _ptr(U), _ptr(W), _ld(W), int(K), _ptr(R), _ld(R),
+        _ptr(C), _ptr(r0), _ptr(c0), _stream(stream)))
+
+
+def gnmppi_mppi_update(C, W, temperature: float, U, weights=None, status=None, K: int | None = None,
+                       stream=None):
+    n = U.numel()
+    K = C.numel() if K is None else K
+    _check("gnmppi_mppi_update", load().gnmppi_mppi_update(
+        _dtype_code(U), n, K, _ptr(C), _ptr(W), _ld(W), float(temperature), _ptr(U),
+        _ptr(weights), _ptr(status), _stream(stream)))
+
+
+def gnmppi_jacobian_workspace(dtype: int, m: int, n: int, K: int) -> int:
+    return int(load().gnmppi_jacobian_workspace(dtype, m, n, K))
+
+
+def gnmppi_reconstruct_jacobian(R, r0, W, J, work, method: int = JAC_LS, sigma2: float = 0.0,
+                                status=None, K: int | None = None, stream=None):
+    m, n = J.shape
+    K = W.shape[1] if K is None else K
+    _check("gnmppi_reconstruct_jacobian", load().gnmppi_reconstruct_jacobian(
+        _dtype_code(J), m, n, K, _ptr(R), _ld(R), _ptr(r0), _ptr(W), _ld(W), int(method),
+        float(sigma2), _ptr(J), _ld(J), _ptr(work), work.numel() * work.element_size(),
+        _ptr(status), _stream(stream)))
+
+
+def gnmppi_ggn_workspace(dtype: int, m: int, n: int) -> int:
+    return int(load().gnmppi_ggn_workspace(dtype, m, n))
+
+
+def gnmppi_ggn_step(J, r0, lm_lambda: float, dU, work, status=None, inc_r0: int = 1, stream=None):
+    m, n = J.shape
+    _check("gnmppi_ggn_step", load().gnmppi_ggn_step(
+        _dtype_code(J), m, n, _ptr(J), _ld(J), _ptr(r0), int(inc_r0), float(lm_lambda), _ptr(dU),
+        _ptr(work), work.numel() * work.element_size(), _ptr(status), _stream(stream)))
+
+
+def gnmppi_line_search(problem, x0, U, dU, alpha, C=None, info=None, stream=None):
+    _check("gnmppi_line_search", load().gnmppi_line_search(
+        ctypes.byref(problem.c), _ptr(x0), _ptr(U), _ptr(dU), _ptr(alpha), alpha.numel(), _ptr(C),
+        _ptr(info), _stream(stream)))
+
+
+def gnmppi_abi_version() -> int:
+    return int(load().gnmppi_abi_version())

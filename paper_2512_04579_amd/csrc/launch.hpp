@@ -1,0 +1,62 @@
+// Host-side launchers of the GN-MPPI kernels.  The C ABI (abi.cpp) validates
+// arguments and calls these; each launcher only enqueues work on `st`.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "gnmppi.h"
+
+namespace gnm {
+
+hipError_t launch_sample(int dtype, int n, int K, double sigma, uint64_t seed,
+                         uint64_t stream_id, int antithetic, void* W, int64_t ldw,
+                         hipStream_t st);
+hipError_t launch_sigma_points(int dtype, int n, double sigma, void* W, int64_t ldw,
+                               hipStream_t st);
+
+hipError_t launch_rollout(const gnmppi_problem& p, const void* x0, const void* U,
+                          const void* W, int64_t ldw, int K, void* R, int64_t ldr,
+                          void* C, void* r0, void* c0, hipStream_t st);
+hipError_t launch_line_search(const gnmppi_problem& p, const void* x0, void* U,
+                              const void* dU, const void* alpha, int L, void* C,
+                              double* info, hipStream_t st);
+
+hipError_t launch_mppi_update(int dtype, int n, int K, const void* C, const void* W,
+                              int64_t ldw, double temperature, void* U, void* weights,
+                              int32_t* status, hipStream_t st);
+
+// Jacobian reconstruction; `work` holds the GEMM partials and G^{-1}.
+struct JacPlan {
+  int nsplit;        // k-splits of the S / G contraction
+  int split_len;     // samples per split (a multiple of the MFMA k-step)
+  int ncol_tiles;    // 16-column tiles covering n
+  int npad;          // 16 * ncol_tiles
+  int rows;          // m (+ n for LS)
+  size_t part_bytes; // bytes of the partial sums
+  size_t ginv_off;   // byte offset of G^{-1} (n x n double) in work
+  size_t total;      // workspace bytes
+};
+JacPlan jacobian_plan(int dtype, int m, int n, int K, int method);
+hipError_t launch_jacobian(int dtype, int m, int n, int K, const void* R, int64_t ldr,
+                           const void* r0, const void* W, int64_t ldw, int method,
+                           double sigma2, void* J, int64_t ldj, void* work,
+                           int32_t* status, hipStream_t st);
+
+struct GgnPlan {
+  int nsplit;        // row chunks of the J^T J contraction
+  int chunk;         // rows per chunk
+  int P;             // n + 1 (augmented with r0)
+  int tiles;         // 64-wide tiles covering P
+  size_t total;      // workspace bytes
+};
+GgnPlan ggn_plan(int dtype, int m, int n);
+hipError_t launch_ggn(int dtype, int m, int n, const void* J, int64_t ldj, const void* r0,
+                      int64_t inc_r0, double lm_lambda, void* dU, void* work,
+                      int32_t* status, hipStream_t st);
+
+// Symmetric sweep (in-place Gauss-Jordan) of a packed SPD matrix in LDS.
+constexpr int kMaxSweepDim = 193;  // n <= 192 plus one augmented row
+
+}  // namespace gnm

@@ -1,0 +1,454 @@
+// Single-shooting rollouts with residuals and costs (Eqs. (1), (2), (4)) and
+// the parallel line search of Eqs. (14)-(15).
+//
+// Mapping.  Double integrator: one lane per sample, the whole state in
+// registers.  Chain: a group of G lanes (G = next power of two >= M, G <= 16)
+// per sample, lane i holding mass i's position and velocity.  The spring
+// force needs the neighbouring masses: lane i reads p_{i-1} and T_{i+1} from
+// the adjacent lanes with one DPP row shift each (no LDS, no barrier), so an
+// RK4 step costs about 100 VALU instructions per lane instead of ~1000 for a
+// lane holding all 64 state entries, and the sequential horizon loop -- the
+// latency that bounds a single MPC instance -- shrinks accordingly.
+//
+// Residual rows are stored sample-fastest (row i of column s at i*ldr + s),
+// so the lanes of a wave that write the same row write consecutive columns.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace gnm {
+namespace {
+
+template <typename T>
+struct ChainDev {
+  int M;
+  T dt, k_lin, k_cub, inv_mass;
+};
+
+// Control of step-k entry idx for a perturbed sample (s >= 0) or the nominal.
+template <typename T>
+struct CtrlPerturbed {
+  const T* __restrict__ U;
+  const T* __restrict__ W;
+  int64_t ldw;
+  int s;
+  __device__ __forceinline__ T operator()(int idx) const {
+    T u = U[idx];
+    if (s >= 0) u += W[idx * ldw + s];
+    return u;
+  }
+};
+
+// Control of a line-search candidate U + alpha dU.
+template <typename T>
+struct CtrlLine {
+  const T* U;  // updated in place by the same kernel after a barrier
+  const T* __restrict__ dU;
+  T alpha;
+  __device__ __forceinline__ T operator()(int idx) const { return U[idx] + alpha * dU[idx]; }
+};
+
+// ---- chain ---------------------------------------------------------------
+
+template <typename T, int G>
+__device__ __forceinline__ void chain_rhs(T px, T py, T vx, T vy, T u0, T u1,
+                                          const ChainDev<T>& cd, bool first, bool free_mass,
+                                          T& dpx, T& dpy, T& dvx, T& dvy) {
+  T qx = 0, qy = 0;
+  if constexpr (G > 1) {
+    qx = dpp_move<kDppRowShr1>(px);
+    qy = dpp_move<kDppRowShr1>(py);
+  }
+  if (first) {  // link 1 is attached to the fixed anchor at the origin
+    qx = 0;
+    qy = 0;
+  }
+  const T dx = px - qx, dy = py - qy;
+  const T s = cd.k_lin + cd.k_cub * (dx * dx + dy * dy);
+  const T tx = s * dx, ty = s * dy;
+  T nx = 0, ny = 0;
+  if constexpr (G > 1) {
+    nx = dpp_move<kDppRowShl1>(tx);
+    ny = dpp_move<kDppRowShl1>(ty);
+  }
+  dpx = free_mass ? vx : u0;
+  dpy = free_mass ? vy : u1;
+  dvx = free_mass ? (nx - tx) * cd.inv_mass : T(0);
+  dvy = free_mass ? (ny - ty) * cd.inv_mass : T(0);
+}
+
+// Rolls out one sample on the G lanes of its group and returns the group's
+// cost 1/2 ||r||^2 (identical in every lane of the group).  All lanes of the
+// wave must call this together (the DPP shifts read neighbouring lanes).
+template <typename T, int G, bool STORE, class Ctrl>
+__device__ __forceinline__ T chain_rollout(const ChainDev<T>& cd, int N,
+                                           const T* __restrict__ x0, const T* __restrict__ q,
+                                           const T* __restrict__ r, const T* __restrict__ xref,
+                                           const Ctrl& ctrl, T* __restrict__ R, int64_t ldr,
+                                           int col, bool store_ok) {
+  const int i = threadIdx.x & (G - 1);
+  const int M = cd.M;
+  const bool has_mass = i < M;
+  const bool free_mass = i < M - 1;
+  const bool first = i == 0;
+  const int ii = has_mass ? i : 0;
+  T px = has_mass ? x0[2 * ii] : T(0);
+  T py = has_mass ? x0[2 * ii + 1] : T(0);
+  T vx = has_mass ? x0[2 * M + 2 * ii] : T(0);
+  T vy = has_mass ? x0[2 * M + 2 * ii + 1] : T(0);
+  const T wpx = dsqrt(T(2) * q[2 * ii]), wpy = dsqrt(T(2) * q[2 * ii + 1]);
+  const T wvx = dsqrt(T(2) * q[2 * M + 2 * ii]), wvy = dsqrt(T(2) * q[2 * M + 2 * ii + 1]);
+  const T rpx = xref[2 * ii], rpy = xref[2 * ii + 1];
+  const T rvx = xref[2 * M + 2 * ii], rvy = xref[2 * M + 2 * ii + 1];
+  const T wu0 = dsqrt(T(2) * r[0]), wu1 = dsqrt(T(2) * r[1]);
+  const int64_t rows_per_step = 4 * M + 2;
+  const T h = cd.dt, hh = T(0.5) * cd.dt, h6 = cd.dt / T(6);
+  T cost = 0;
+  for (int k = 0; k < N; ++k) {
+    const T u0 = ctrl(2 * k), u1 = ctrl(2 * k + 1);
+    T a_px, a_py, a_vx, a_vy, b_px, b_py, b_vx, b_vy;
+    chain_rhs<T, G>(px, py, vx, vy, u0, u1, cd, first, free_mass, a_px, a_py, a_vx, a_vy);
+    T s_px = a_px, s_py = a_py, s_vx = a_vx, s_vy = a_vy;  // running k1 + 2 k2 + 2 k3 + k4
+    chain_rhs<T, G>(px + hh * a_px, py + hh * a_py, vx + hh * a_vx, vy + hh * a_vy, u0, u1, cd,
+                    first, free_mass, b_px, b_py, b_vx, b_vy);
+    s_px += T(2) * b_px; s_py += T(2) * b_py; s_vx += T(2) * b_vx; s_vy += T(2) * b_vy;
+    chain_rhs<T, G>(px + hh * b_px, py + hh * b_py, vx + hh * b_vx, vy + hh * b_vy, u0, u1, cd,
+                    first, free_mass, a_px, a_py, a_vx, a_vy);
+    s_px += T(2) * a_px; s_py += T(2) * a_py; s_vx += T(2) * a_vx; s_vy += T(2) * a_vy;
+    chain_rhs<T, G>(px + h * a_px, py + h * a_py, vx + h * a_vx, vy + h * a_vy, u0, u1, cd,
+                    first, free_mass, b_px, b_py, b_vx, b_vy);
+    s_px += b_px; s_py += b_py; s_vx += b_vx; s_vy += b_vy;
+    px += h6 * s_px;
+    py += h6 * s_py;
+    vx += h6 * s_vx;
+    vy += h6 * s_vy;
+    if (!free_mass) {  // the end mass moves with the commanded velocity
+      vx = u0;
+      vy = u1;
+    }
+    const T e0 = wpx * (px - rpx), e1 = wpy * (py - rpy);
+    const T e2 = wvx * (vx - rvx), e3 = wvy * (vy - rvy);
+    const T f0 = wu0 * u0, f1 = wu1 * u1;
+    if (has_mass) cost += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
+    if (first) cost += f0 * f0 + f1 * f1;
+    if constexpr (STORE) {
+      if (store_ok) {
+        const int64_t base = k * rows_per_step;
+        if (has_mass) {
+          R[(base + 2 * i) * ldr + col] = e0;
+          R[(base + 2 * i + 1) * ldr + col] = e1;
+          R[(base + 2 * M + 2 * i) * ldr + col] = e2;
+          R[(base + 2 * M + 2 * i + 1) * ldr + col] = e3;
+        }
+        if (first) {
+          R[(base + 4 * M) * ldr + col] = f0;
+          R[(base + 4 * M + 1) * ldr + col] = f1;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) cost += __shfl_xor(cost, off, kWave);
+  return T(0.5) * cost;
+}
+
+template <typename T, int G>
+__global__ void __launch_bounds__(256) rollout_chain_kernel(
+    ChainDev<T> cd, int N, const T* __restrict__ x0, const T* __restrict__ q,
+    const T* __restrict__ r, const T* __restrict__ xref, const T* __restrict__ U,
+    const T* __restrict__ W, int64_t ldw, int K, T* __restrict__ R, int64_t ldr,
+    T* __restrict__ C, T* __restrict__ r0, T* __restrict__ c0) {
+  const int ncol = K + (c0 ? 1 : 0);
+  const int gcol = (blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const bool valid = gcol < ncol;
+  const int col = valid ? gcol : ncol - 1;  // idle groups repeat a valid column, never store
+  const bool nominal = col == K;
+  CtrlPerturbed<T> ctrl{U, W, ldw, (nominal || W == nullptr) ? -1 : col};
+  T* out = nominal ? r0 : R;
+  const int64_t ld = nominal ? 1 : ldr;
+  const int ocol = nominal ? 0 : col;
+  T c;
+  if (R != nullptr || r0 != nullptr)
+    c = chain_rollout<T, G, true>(cd, N, x0, q, r, xref, ctrl, out, ld, ocol,
+                                  valid && out != nullptr);
+  else
+    c = chain_rollout<T, G, false>(cd, N, x0, q, r, xref, ctrl, nullptr, 0, 0, false);
+  if (valid && (threadIdx.x & (G - 1)) == 0) {
+    if (nominal)
+      c0[0] = c;
+    else
+      C[col] = c;
+  }
+}
+
+// ---- double integrator -----------------------------------------------------
+
+template <typename T, int D, bool STORE, class Ctrl>
+__device__ __forceinline__ T di_rollout(int N, T dt, const T* __restrict__ x0,
+                                        const T* __restrict__ q, const T* __restrict__ r,
+                                        const T* __restrict__ xref, const Ctrl& ctrl,
+                                        T* __restrict__ R, int64_t ldr, int col, bool store_ok) {
+  T p[D], v[D], wp[D], wv[D], wu[D], rp[D], rv[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    p[j] = x0[j];
+    v[j] = x0[D + j];
+    wp[j] = dsqrt(T(2) * q[j]);
+    wv[j] = dsqrt(T(2) * q[D + j]);
+    wu[j] = dsqrt(T(2) * r[j]);
+    rp[j] = xref[j];
+    rv[j] = xref[D + j];
+  }
+  const T hdt2 = T(0.5) * dt * dt;
+  T cost = 0;
+  for (int k = 0; k < N; ++k) {
+    const int64_t base = static_cast<int64_t>(k) * 3 * D;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const T u = ctrl(k * D + j);
+      p[j] = p[j] + dt * v[j] + hdt2 * u;
+      v[j] = v[j] + dt * u;
+      const T e0 = wp[j] * (p[j] - rp[j]);
+      const T e1 = wv[j] * (v[j] - rv[j]);
+      const T e2 = wu[j] * u;
+      cost += e0 * e0 + e1 * e1 + e2 * e2;
+      if constexpr (STORE) {
+        if (store_ok) {
+          R[(base + j) * ldr + col] = e0;
+          R[(base + D + j) * ldr + col] = e1;
+          R[(base + 2 * D + j) * ldr + col] = e2;
+        }
+      }
+    }
+  }
+  return T(0.5) * cost;
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256) rollout_di_kernel(
+    int N, T dt, const T* __restrict__ x0, const T* __restrict__ q, const T* __restrict__ r,
+    const T* __restrict__ xref, const T* __restrict__ U, const T* __restrict__ W, int64_t ldw,
+    int K, T* __restrict__ R, int64_t ldr, T* __restrict__ C, T* __restrict__ r0,
+    T* __restrict__ c0) {
+  const int ncol = K + (c0 ? 1 : 0);
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= ncol) return;  // no cross-lane traffic here, so idle lanes may leave
+  const bool nominal = col == K;
+  CtrlPerturbed<T> ctrl{U, W, ldw, (nominal || W == nullptr) ? -1 : col};
+  T* out = nominal ? r0 : R;
+  const int64_t ld = nominal ? 1 : ldr;
+  const int ocol = nominal ? 0 : col;
+  T c;
+  if (out != nullptr)
+    c = di_rollout<T, D, true>(N, dt, x0, q, r, xref, ctrl, out, ld, ocol, true);
+  else
+    c = di_rollout<T, D, false>(N, dt, x0, q, r, xref, ctrl, nullptr, 0, 0, false);
+  if (nominal)
+    c0[0] = c;
+  else
+    C[col] = c;
+}
+
+// ---- line search (Eqs. (14)-(15)) -------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ void line_select_and_apply(T* costs, int L, int n, T* U,
+                                                      const T* __restrict__ dU,
+                                                      const T* __restrict__ alpha,
+                                                      T* __restrict__ Cout, double* info,
+                                                      int* jstar) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int best = -1;
+    T bc = 0;
+    for (int t = 0; t < L; ++t) {
+      const T v = costs[t];
+      if (finite(v) && (best < 0 || v < bc)) {
+        best = t;
+        bc = v;
+      }
+    }
+    *jstar = best;
+    if (Cout)
+      for (int t = 0; t < L; ++t) Cout[t] = costs[t];
+    if (info) {
+      info[0] = best >= 0 ? static_cast<double>(alpha[best]) : 0.0;
+      info[1] = best >= 0 ? static_cast<double>(bc) : __builtin_nan("");
+      info[2] = static_cast<double>(best);
+    }
+  }
+  __syncthreads();
+  const int b = *jstar;
+  if (b >= 0) {
+    const T a = alpha[b];
+    for (int t = threadIdx.x; t < n; t += blockDim.x) U[t] = U[t] + a * dU[t];
+  }
+}
+
+template <typename T, int G>
+__global__ void __launch_bounds__(1024) line_search_chain_kernel(
+    ChainDev<T> cd, int N, const T* __restrict__ x0, const T* __restrict__ q,
+    const T* __restrict__ r, const T* __restrict__ xref, T* U, const T* __restrict__ dU,
+    const T* __restrict__ alpha, int L, T* __restrict__ Cout, double* info) {
+  __shared__ T costs[64];
+  __shared__ int jstar;
+  const int j = threadIdx.x / G;
+  const int jj = j < L ? j : L - 1;
+  CtrlLine<T> ctrl{U, dU, alpha[jj]};
+  const T c = chain_rollout<T, G, false>(cd, N, x0, q, r, xref, ctrl, nullptr, 0, 0, false);
+  if (j < L && (threadIdx.x & (G - 1)) == 0) costs[j] = c;
+  line_select_and_apply(costs, L, N * 2, U, dU, alpha, Cout, info, &jstar);
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(64) line_search_di_kernel(
+    int N, T dt, const T* __restrict__ x0, const T* __restrict__ q, const T* __restrict__ r,
+    const T* __restrict__ xref, T* U, const T* __restrict__ dU, const T* __restrict__ alpha,
+    int L, T* __restrict__ Cout, double* info) {
+  __shared__ T costs[64];
+  __shared__ int jstar;
+  const int j = threadIdx.x;
+  if (j < L) {
+    CtrlLine<T> ctrl{U, dU, alpha[j]};
+    costs[j] = di_rollout<T, D, false>(N, dt, x0, q, r, xref, ctrl, nullptr, 0, 0, false);
+  }
+  line_select_and_apply(costs, L, N * D, U, dU, alpha, Cout, info, &jstar);
+}
+
+// ---- dispatch ---------------------------------------------------------------
+
+inline int chain_group(int M) {
+  int g = 1;
+  while (g < M) g <<= 1;
+  return g;
+}
+
+template <typename T>
+ChainDev<T> chain_dev(const gnmppi_problem& p) {
+  return ChainDev<T>{p.n_masses, static_cast<T>(p.dt), static_cast<T>(p.k_lin),
+                     static_cast<T>(p.k_cub), static_cast<T>(1.0 / p.mass)};
+}
+
+template <typename T>
+hipError_t rollout_typed(const gnmppi_problem& p, const T* x0, const T* U, const T* W,
+                         int64_t ldw, int K, T* R, int64_t ldr, T* C, T* r0, T* c0,
+                         hipStream_t st) {
+  const T* q = static_cast<const T*>(p.q);
+  const T* r = static_cast<const T*>(p.r);
+  const T* xr = static_cast<const T*>(p.x_ref);
+  const int ncol = K + (c0 ? 1 : 0);
+  if (p.model == GNMPPI_MODEL_CHAIN) {
+    const ChainDev<T> cd = chain_dev<T>(p);
+    const int G = chain_group(p.n_masses);
+    const int threads = ncol * G;
+    dim3 grid((threads + 255) / 256);
+#define GNM_CHAIN_CASE(GG)                                                                      \
+  case GG:                                                                                      \
+    hipLaunchKernelGGL((rollout_chain_kernel<T, GG>), grid, dim3(256), 0, st, cd, p.N, x0, q,   \
+                       r, xr, U, W, ldw, K, R, ldr, C, r0, c0);                                 \
+    break;
+    switch (G) {
+      GNM_CHAIN_CASE(1)
+      GNM_CHAIN_CASE(2)
+      GNM_CHAIN_CASE(4)
+      GNM_CHAIN_CASE(8)
+      GNM_CHAIN_CASE(16)
+      default:
+        return hipErrorInvalidValue;
+    }
+#undef GNM_CHAIN_CASE
+  } else {
+    dim3 grid((ncol + 255) / 256);
+    const T dt = static_cast<T>(p.dt);
+#define GNM_DI_CASE(DD)                                                                          \
+  case DD:                                                                                       \
+    hipLaunchKernelGGL((rollout_di_kernel<T, DD>), grid, dim3(256), 0, st, p.N, dt, x0, q, r, xr, \
+                       U, W, ldw, K, R, ldr, C, r0, c0);                                         \
+    break;
+    switch (p.nu) {
+      GNM_DI_CASE(1)
+      GNM_DI_CASE(2)
+      GNM_DI_CASE(3)
+      GNM_DI_CASE(4)
+      default:
+        return hipErrorInvalidValue;
+    }
+#undef GNM_DI_CASE
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t line_search_typed(const gnmppi_problem& p, const T* x0, T* U, const T* dU,
+                             const T* alpha, int L, T* C, double* info, hipStream_t st) {
+  const T* q = static_cast<const T*>(p.q);
+  const T* r = static_cast<const T*>(p.r);
+  const T* xr = static_cast<const T*>(p.x_ref);
+  if (p.model == GNMPPI_MODEL_CHAIN) {
+    const ChainDev<T> cd = chain_dev<T>(p);
+    const int G = chain_group(p.n_masses);
+    const int threads = ((L * G + 63) / 64) * 64;
+#define GNM_LS_CASE(GG)                                                                          \
+  case GG:                                                                                       \
+    hipLaunchKernelGGL((line_search_chain_kernel<T, GG>), dim3(1), dim3(threads), 0, st, cd, p.N, \
+                       x0, q, r, xr, U, dU, alpha, L, C, info);                                  \
+    break;
+    switch (G) {
+      GNM_LS_CASE(1)
+      GNM_LS_CASE(2)
+      GNM_LS_CASE(4)
+      GNM_LS_CASE(8)
+      GNM_LS_CASE(16)
+      default:
+        return hipErrorInvalidValue;
+    }
+#undef GNM_LS_CASE
+  } else {
+    const T dt = static_cast<T>(p.dt);
+#define GNM_LSD_CASE(DD)                                                                      \
+  case DD:                                                                                    \
+    hipLaunchKernelGGL((line_search_di_kernel<T, DD>), dim3(1), dim3(64), 0, st, p.N, dt, x0, q, \
+                       r, xr, U, dU, alpha, L, C, info);                                      \
+    break;
+    switch (p.nu) {
+      GNM_LSD_CASE(1)
+      GNM_LSD_CASE(2)
+      GNM_LSD_CASE(3)
+      GNM_LSD_CASE(4)
+      default:
+        return hipErrorInvalidValue;
+    }
+#undef GNM_LSD_CASE
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_rollout(const gnmppi_problem& p, const void* x0, const void* U, const void* W,
+                          int64_t ldw, int K, void* R, int64_t ldr, void* C, void* r0, void* c0,
+                          hipStream_t st) {
+  if (p.dtype == GNMPPI_F32)
+    return rollout_typed<float>(p, static_cast<const float*>(x0), static_cast<const float*>(U),
+                                static_cast<const float*>(W), ldw, K, static_cast<float*>(R), ldr,
+                                static_cast<float*>(C), static_cast<float*>(r0),
+                                static_cast<float*>(c0), st);
+  return rollout_typed<double>(p, static_cast<const double*>(x0), static_cast<const double*>(U),
+                               static_cast<const double*>(W), ldw, K, static_cast<double*>(R),
+                               ldr, static_cast<double*>(C), static_cast<double*>(r0),
+                               static_cast<double*>(c0), st);
+}
+
+hipError_t launch_line_search(const gnmppi_problem& p, const void* x0, void* U, const void* dU,
+                              const void* alpha, int L, void* C, double* info, hipStream_t st) {
+  if (p.dtype == GNMPPI_F32)
+    return line_search_typed<float>(p, static_cast<const float*>(x0), static_cast<float*>(U),
+                                    static_cast<const float*>(dU),
+                                    static_cast<const float*>(alpha), L, static_cast<float*>(C),
+                                    info, st);
+  return line_search_typed<double>(p, static_cast<const double*>(x0), static_cast<double*>(U),
+                                   static_cast<const double*>(dU),
+                                   static_cast<const double*>(alpha), L, static_cast<double*>(C),
+                                   info, st);
+}
+
+}  // namespace gnm

@@ -1,0 +1,130 @@
+// Perturbation sampling (Sec. 3: W ~ N(0, Sigma); antithetic pairs as in
+// Sec. 5) and the Dirac-mixture set of Method E (Sec. 5).
+//
+// One thread draws one Philox4x32-10 block (Salmon et al., SC'11): four
+// 32-bit words for a fixed (column, row block).  FP32 turns the block into
+// four normals (two Box-Muller pairs), FP64 into two.  Threads of a wave take
+// consecutive columns, so every store is a coalesced 256/512-byte row segment
+// of the sample-fastest W.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace gnm {
+namespace {
+
+struct Philox4x32 {
+  uint32_t c0, c1, c2, c3;
+};
+
+__device__ __forceinline__ Philox4x32 philox4x32_10(Philox4x32 c, uint32_t k0, uint32_t k1) {
+  constexpr uint32_t kMul0 = 0xD2511F53u, kMul1 = 0xCD9E8D57u;
+  constexpr uint32_t kWeyl0 = 0x9E3779B9u, kWeyl1 = 0xBB67AE85u;
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint32_t hi0 = __umulhi(kMul0, c.c0), lo0 = kMul0 * c.c0;
+    const uint32_t hi1 = __umulhi(kMul1, c.c2), lo1 = kMul1 * c.c2;
+    c = Philox4x32{hi1 ^ c.c1 ^ k0, lo1, hi0 ^ c.c3 ^ k1, lo0};
+    k0 += kWeyl0;
+    k1 += kWeyl1;
+  }
+  return c;
+}
+
+// Box-Muller from two 32-bit words: u1 in (0, 1] (never 0, so the log is
+// finite), u2 in [0, 1).  24-bit uniforms are exact in float.
+__device__ __forceinline__ void box_muller_f32(uint32_t a, uint32_t b, float& z0, float& z1) {
+  const float u1 = static_cast<float>((a >> 8) + 1u) * 0x1.0p-24f;
+  const float u2 = static_cast<float>(b >> 8) * 0x1.0p-24f;
+  const float rad = __builtin_sqrtf(-2.0f * logf(u1));
+  float s, c;
+  sincospif(2.0f * u2, &s, &c);
+  z0 = rad * c;
+  z1 = rad * s;
+}
+
+__device__ __forceinline__ void box_muller_f64(Philox4x32 x, double& z0, double& z1) {
+  const uint64_t a = (static_cast<uint64_t>(x.c0) << 21) | (x.c1 >> 11);
+  const uint64_t b = (static_cast<uint64_t>(x.c2) << 21) | (x.c3 >> 11);
+  const double u1 = static_cast<double>(a + 1u) * 0x1.0p-53;
+  const double u2 = static_cast<double>(b) * 0x1.0p-53;
+  const double rad = __builtin_sqrt(-2.0 * log(u1));
+  double s, c;
+  sincospi(2.0 * u2, &s, &c);
+  z0 = rad * c;
+  z1 = rad * s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) sample_kernel(int n, int Kdraw, T sigma, uint32_t k0,
+                                                     uint32_t k1, uint32_t s0, uint32_t s1,
+                                                     int antithetic, T* __restrict__ W,
+                                                     int64_t ldw) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (s >= Kdraw) return;
+  const Philox4x32 x = philox4x32_10(Philox4x32{static_cast<uint32_t>(s), static_cast<uint32_t>(b), s0, s1}, k0, k1);
+  constexpr int kRows = sizeof(T) == 4 ? 4 : 2;
+  T z[kRows];
+  if constexpr (sizeof(T) == 4) {
+    box_muller_f32(x.c0, x.c1, z[0], z[1]);
+    box_muller_f32(x.c2, x.c3, z[2], z[3]);
+  } else {
+    box_muller_f64(x, z[0], z[1]);
+  }
+#pragma unroll
+  for (int t = 0; t < kRows; ++t) {
+    const int row = kRows * b + t;
+    if (row < n) {
+      const T v = sigma * z[t];
+      W[row * ldw + s] = v;
+      if (antithetic) W[row * ldw + s + Kdraw] = -v;
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) sigma_points_kernel(int n, T scale, T* __restrict__ W,
+                                                           int64_t ldw) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = blockIdx.y;
+  if (s >= 2 * n) return;
+  T v = 0;
+  if (s == row) v = scale;
+  if (s == row + n) v = -scale;
+  W[row * ldw + s] = v;
+}
+
+}  // namespace
+
+hipError_t launch_sample(int dtype, int n, int K, double sigma, uint64_t seed,
+                         uint64_t stream_id, int antithetic, void* W, int64_t ldw,
+                         hipStream_t st) {
+  const int Kdraw = antithetic ? K / 2 : K;
+  const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
+  const uint32_t s0 = static_cast<uint32_t>(stream_id), s1 = static_cast<uint32_t>(stream_id >> 32);
+  const int rows_per_block = dtype == GNMPPI_F32 ? 4 : 2;
+  dim3 grid((Kdraw + 255) / 256, (n + rows_per_block - 1) / rows_per_block);
+  if (dtype == GNMPPI_F32)
+    hipLaunchKernelGGL(sample_kernel<float>, grid, dim3(256), 0, st, n, Kdraw,
+                       static_cast<float>(sigma), k0, k1, s0, s1, antithetic,
+                       static_cast<float*>(W), ldw);
+  else
+    hipLaunchKernelGGL(sample_kernel<double>, grid, dim3(256), 0, st, n, Kdraw, sigma, k0, k1,
+                       s0, s1, antithetic, static_cast<double*>(W), ldw);
+  return hipGetLastError();
+}
+
+hipError_t launch_sigma_points(int dtype, int n, double sigma, void* W, int64_t ldw,
+                               hipStream_t st) {
+  dim3 grid((2 * n + 255) / 256, n);
+  const double scale = __builtin_sqrt(static_cast<double>(n)) * sigma;
+  if (dtype == GNMPPI_F32)
+    hipLaunchKernelGGL(sigma_points_kernel<float>, grid, dim3(256), 0, st, n,
+                       static_cast<float>(scale), static_cast<float*>(W), ldw);
+  else
+    hipLaunchKernelGGL(sigma_points_kernel<double>, grid, dim3(256), 0, st, n, scale,
+                       static_cast<double*>(W), ldw);
+  return hipGetLastError();
+}
+
+}  // namespace gnm

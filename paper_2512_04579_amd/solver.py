@@ -1,0 +1,190 @@
+"""Outer loops built from the C-ABI calls: Alg. 1 (GN-MPPI, Methods D and E)
+and deterministic MPPI (Method C).
+
+Each iteration only enqueues library calls on the current stream; the step
+length, the new cost and every status word stay in device memory, so an
+iteration never waits for the GPU and can be captured into a HIP graph.  The
+host computes only the scalar sampling scale of the iteration.
+
+Readings of the paper used here: Alg. 1 shrinks the covariance,
+Sigma_{k+1} = beta Sigma_k, so the sampler's scale is
+sigma_k = max(sigma_0 beta^(k/2), sigma_min); the step-length set is
+{gamma^j : j < L}; the GGN step uses the nominal residual R(U_k).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib
+from .problem import DeviceProblem
+
+_ALIGN = 64  # leading dimensions are padded to 64 elements (256 B for float)
+
+
+def _round_up(v: int, a: int = _ALIGN) -> int:
+    return (v + a - 1) // a * a
+
+
+def sigma_schedule(sigma0: float, beta: float, sigma_min: float, it: int) -> float:
+    return max(sigma0 * beta ** (0.5 * it), sigma_min)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    t = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+    if t.data_ptr() % 256:
+        raise RuntimeError("workspace is not 256-byte aligned")
+    return t
+
+
+class _Ticker:
+    """Records (start, end) CUDA/HIP events around consecutive calls."""
+
+    def __init__(self, marks):
+        self.marks = marks
+        self.name = None
+        self.ev = None
+
+    def _event(self):
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        return e
+
+    def start(self, name):
+        if self.marks is not None:
+            self.name, self.ev = name, self._event()
+
+    def next(self, name):
+        if self.marks is not None:
+            e = self._event()
+            self.marks.setdefault(self.name, []).append((self.ev, e))
+            self.name, self.ev = name, e
+
+    def stop(self):
+        if self.marks is not None:
+            e = self._event()
+            self.marks.setdefault(self.name, []).append((self.ev, e))
+
+
+class GNMPPI:
+    """Alg. 1 on the GPU.  ``sampler`` is "gaussian" (Method D, antithetic
+    Philox normals) or "sigma_points" (Method E, the 2n-point Dirac mixture)."""
+
+    def __init__(self, dprob: DeviceProblem, x0, settings, seed: int = 1, U0=None,
+                 sampler: str = "gaussian", max_iters: int | None = None):
+        self.p = dprob
+        self.s = settings
+        self.seed = int(seed)
+        self.sampler = sampler
+        n, m = dprob.n, dprob.m
+        dev, dt = dprob.device, dprob.tdtype
+        self.K = 2 * n if sampler == "sigma_points" else settings.K
+        K = self.K
+        self.n, self.m = n, m
+        self.x0 = dprob.tensor(x0)
+        self.U = torch.zeros(n, dtype=dt, device=dev) if U0 is None else dprob.tensor(U0)
+        self.W = torch.zeros(n, _round_up(K), dtype=dt, device=dev)
+        self.R = torch.zeros(m, _round_up(K), dtype=dt, device=dev)
+        self.C = torch.zeros(K, dtype=dt, device=dev)
+        self.r0 = torch.zeros(m, dtype=dt, device=dev)
+        self.c0 = torch.zeros(1, dtype=dt, device=dev)
+        self.J = torch.zeros(m, n, dtype=dt, device=dev)
+        self.dU = torch.zeros(n, dtype=dt, device=dev)
+        self.alpha = torch.tensor([settings.gamma ** j for j in range(settings.n_alpha)],
+                                  dtype=dt, device=dev)
+        self.C_line = torch.zeros(settings.n_alpha, dtype=dt, device=dev)
+        iters = max_iters if max_iters is not None else settings.iters
+        self.info = torch.zeros(max(iters, 1), 3, dtype=torch.float64, device=dev)
+        self.status = torch.zeros(iters if iters else 1, 2, dtype=torch.int32, device=dev)
+        code = _lib.F32 if dt == torch.float32 else _lib.F64
+        self.work_j = _workspace(_lib.gnmppi_jacobian_workspace(code, m, n, K), dev)
+        self.work_g = _workspace(_lib.gnmppi_ggn_workspace(code, m, n), dev)
+        self.method = _lib.JAC_LS if settings.jacobian == "ls" else _lib.JAC_MC
+
+    def sigma(self, it: int) -> float:
+        s = self.s
+        return sigma_schedule(s.sigma0, s.beta, s.sigma_min, it)
+
+    def step(self, it: int, marks=None):
+        """One iteration of Alg. 1: GetJacobian, full GGN step, line search,
+        apply; the covariance shrink enters through ``sigma(it)``.  With
+        ``marks`` (a dict name -> list), a pair of timing events is recorded
+        around each library call on the current stream."""
+        K, sig = self.K, self.sigma(it)
+        W = self.W[:, :K]
+        tick = _Ticker(marks)
+        tick.start("sample")
+        if self.sampler == "sigma_points":
+            _lib.gnmppi_sigma_points(W, sig)
+        else:
+            _lib.gnmppi_sample(W, sig, self.seed, it, antithetic=self.s.antithetic, K=K)
+        tick.next("rollout")
+        _lib.gnmppi_rollout(self.p, self.x0, self.U, W, K, self.R[:, :K], self.C, self.r0, self.c0)
+        tick.next("jacobian")
+        _lib.gnmppi_reconstruct_jacobian(self.R[:, :K], self.r0, W, self.J, self.work_j,
+                                         self.method, sig * sig, self.status[it, 0:1], K)
+        tick.next("ggn_step")
+        _lib.gnmppi_ggn_step(self.J, self.r0, self.s.lm_lambda, self.dU, self.work_g,
+                             self.status[it, 1:2])
+        tick.next("line_search")
+        _lib.gnmppi_line_search(self.p, self.x0, self.U, self.dU, self.alpha, self.C_line,
+                                self.info[it])
+        tick.stop()
+
+    def solve(self, iters: int | None = None, events: bool = False):
+        """Runs ``iters`` iterations; returns (costs, alphas, statuses, event list)."""
+        iters = self.s.iters if iters is None else iters
+        evs = []
+        if events:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            evs.append(e0)
+        for it in range(iters):
+            self.step(it)
+            if events:
+                e = torch.cuda.Event(enable_timing=True)
+                e.record()
+                evs.append(e)
+        return evs
+
+    def history(self, iters: int):
+        info = self.info[:iters].cpu()
+        return info[:, 1].double().numpy(), info[:, 0].double().numpy(), self.status[:iters].cpu().numpy()
+
+
+class PlainMPPI:
+    """Method C: U <- U + sum_s w_s W_s / sum_s w_s (Eqs. (7)-(8)).  The
+    rollout of each iteration also evaluates the nominal U, so cost[it] holds
+    C(U_it) without an extra launch."""
+
+    def __init__(self, dprob: DeviceProblem, x0, settings, seed: int = 2, U0=None,
+                 max_iters: int = 1000):
+        self.p = dprob
+        self.s = settings
+        self.seed = int(seed)
+        n = dprob.n
+        dev, dt = dprob.device, dprob.tdtype
+        K = settings.K
+        self.K = K
+        self.x0 = dprob.tensor(x0)
+        self.U = torch.zeros(n, dtype=dt, device=dev) if U0 is None else dprob.tensor(U0)
+        self.W = torch.zeros(n, _round_up(K), dtype=dt, device=dev)
+        self.C = torch.zeros(K, dtype=dt, device=dev)
+        self.cost = torch.zeros(max_iters + 1, dtype=dt, device=dev)
+        self.status = torch.zeros(max_iters + 1, dtype=torch.int32, device=dev)
+        self.sigma0 = settings.mppi_sigma0 or settings.sigma0
+
+    def sigma(self, it: int) -> float:
+        return sigma_schedule(self.sigma0, self.s.mppi_beta, 0.0, it)
+
+    def step(self, it: int):
+        K = self.K
+        W = self.W[:, :K]
+        _lib.gnmppi_sample(W, self.sigma(it), self.seed, it, antithetic=self.s.antithetic, K=K)
+        _lib.gnmppi_rollout(self.p, self.x0, self.U, W, K, None, self.C, None, self.cost[it:it + 1])
+        _lib.gnmppi_mppi_update(self.C, W, self.s.temperature, self.U, None,
+                                self.status[it:it + 1], K)
+
+    def final_cost(self, it: int):
+        """Enqueues the nominal rollout of the current U into cost[it]."""
+        _lib.gnmppi_rollout(self.p, self.x0, self.U, None, 0, None, None, None,
+                            self.cost[it:it + 1])

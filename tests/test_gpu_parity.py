@@ -1,0 +1,418 @@
+"""GPU parity: each C-ABI call against the FP64 oracle on identical seeded,
+dtype-rounded inputs (float32 <= 1e-4, float64 <= 1e-10 normwise relative).
+
+Cases span several tiles with ragged tails, the full c2 shapes (chain16,
+N=50, K=4096, the launch configuration the benchmark times), the limits
+(n = 192, L = 1 and 64, K = 0 and 1, a single-mass chain) and the
+degenerate inputs (non-finite costs, rank-deficient perturbations, a
+singular normal matrix).
+"""
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from _parity import TOL, assert_parity, device, host, padded, rel_err, rnd, round_problem, to_dev
+from oracle import dynamics, ggn, jacobian, lqr, mppi, ocp, philox, sigma_points, solvers
+from paper_2512_04579_amd import _lib
+from paper_2512_04579_amd.problem import DeviceProblem
+from paper_2512_04579_amd.solver import GNMPPI, PlainMPPI
+
+pytestmark = pytest.mark.gpu
+
+
+def _sync():
+    torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# a1: sampler
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype,n,K,anti", [("f32", 37, 300, True), ("f64", 37, 300, True),
+                                             ("f32", 100, 4096, True), ("f32", 5, 77, False),
+                                             ("f64", 3, 1, False)])
+def test_sampler_matches_philox_definition(dtype, n, K, anti):
+    dev = device()
+    W = padded(np.zeros((n, K)), dtype)
+    _lib.gnmppi_sample(W, 0.3, seed=0x1234_5678_9ABC, stream_id=7, antithetic=anti, K=K)
+    _sync()
+    ref = philox.perturbations(n, K, 0.3, seed=0x1234_5678_9ABC, stream=7, dtype=dtype, antithetic=anti)
+    got = host(W)
+    tol = 2e-6 if dtype == "f32" else 1e-13
+    np.testing.assert_allclose(got, ref, rtol=tol, atol=tol)
+    if anti:
+        np.testing.assert_array_equal(got[:, K // 2:], -got[:, :K // 2])
+
+
+def test_sigma_points_match_method_e_set():
+    n = 40
+    W = padded(np.zeros((n, 2 * n)), "f64")
+    _lib.gnmppi_sigma_points(W, 0.25)
+    _sync()
+    np.testing.assert_allclose(host(W), sigma_points.symmetric_set(n, 0.25), rtol=1e-15, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# a2: rollout
+# ---------------------------------------------------------------------------
+
+def _rollout_case(name):
+    if name == "c1":
+        w = wl.c1()
+        return w.problem, w.x0, "f64", 256, True
+    if name == "c2":
+        w = wl.c2()
+        return w.problem, w.x0, "f32", 4096, True
+    if name == "di_axis_N50_ragged":
+        p = wl.double_integrator_problem(axes=1, N=50)
+        return p, np.array([0.7, -0.3]), "f64", 301, False
+    if name == "chain3_f32_ragged":
+        p, x0 = wl.chain_problem(n_masses=3, N=6, seed=3)
+        return p, x0, "f32", 300, True
+    if name == "chain5_f64_padding_lanes":
+        p, x0 = wl.chain_problem(n_masses=5, N=7, seed=4)
+        return p, x0, "f64", 257, False
+    if name == "chain1_f32":
+        p, x0 = wl.chain_problem(n_masses=1, N=4, seed=5)
+        return p, x0, "f32", 65, False
+    if name == "chain16_f64":
+        p, x0 = wl.chain_problem(n_masses=16, N=12, seed=6)
+        return p, x0, "f64", 128, True
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "di_axis_N50_ragged", "chain3_f32_ragged",
+                                  "chain5_f64_padding_lanes", "chain1_f32", "chain16_f64"])
+def test_rollout_matches_oracle(name):
+    prob, x0, dtype, K, anti = _rollout_case(name)
+    dev = device()
+    rp = round_problem(prob, dtype)
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    U = rnd(0.2 * rng.standard_normal(prob.n), dtype)
+    W = rnd(wl.gaussian_perturbations(prob.n, K, 0.3, 11, antithetic=anti), dtype)
+    x0r = rnd(x0, dtype)
+    dp = DeviceProblem(prob, dtype)
+    Wd, Rd = padded(W, dtype), padded(np.zeros((prob.m, K)), dtype)
+    Cd = to_dev(np.zeros(K), dtype)
+    r0d, c0d = to_dev(np.zeros(prob.m), dtype), to_dev(np.zeros(1), dtype)
+    x0d, Ud = to_dev(x0r, dtype), to_dev(U, dtype)
+    _lib.gnmppi_rollout(dp, x0d, Ud, Wd, K, Rd, Cd, r0d, c0d)
+    # costs-only launch must reproduce the stored-run costs bit for bit
+    C2 = to_dev(np.zeros(K), dtype)
+    _lib.gnmppi_rollout(dp, x0d, Ud, Wd, K, None, C2)
+    _sync()
+    R_ref, C_ref = ocp.rollout_batch(rp, x0r, U, W, nominal=True)
+    assert_parity(host(Rd), R_ref[:, 1:], dtype, "R")
+    assert_parity(host(Cd), C_ref[1:], dtype, "C")
+    assert_parity(host(r0d), R_ref[:, 0], dtype, "r0")
+    assert_parity(host(c0d), C_ref[:1], dtype, "c0")
+    np.testing.assert_array_equal(host(C2), host(Cd))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_rollout_nominal_only_and_single_sample(dtype):
+    prob, x0 = wl.chain_problem(n_masses=4, N=9, seed=8)
+    rp = round_problem(prob, dtype)
+    dp = DeviceProblem(prob, dtype)
+    U = rnd(np.linspace(-0.5, 0.5, prob.n), dtype)
+    x0r = rnd(x0, dtype)
+    c0 = to_dev(np.zeros(1), dtype)
+    r0 = to_dev(np.zeros(prob.m), dtype)
+    _lib.gnmppi_rollout(dp, to_dev(x0r, dtype), to_dev(U, dtype), None, 0, None, None, r0, c0)
+    W1 = rnd(0.1 * np.ones((prob.n, 1)), dtype)
+    C1 = to_dev(np.zeros(1), dtype)
+    _lib.gnmppi_rollout(dp, to_dev(x0r, dtype), to_dev(U, dtype), padded(W1, dtype), 1, None, C1)
+    _sync()
+    assert_parity(host(r0), ocp.residual(rp, x0r, U), dtype, "r0")
+    assert_parity(host(c0), [ocp.cost(rp, x0r, U)], dtype, "c0")
+    assert_parity(host(C1), [ocp.cost(rp, x0r, U + W1[:, 0])], dtype, "C1")
+
+
+def test_chain_rest_pose_is_a_fixed_point_on_device():
+    prob, _ = wl.chain_problem(n_masses=16, N=50, seed=2)
+    dp = DeviceProblem(prob, "f64")
+    c0 = to_dev(np.ones(1), "f64")
+    r0 = to_dev(np.ones(prob.m), "f64")
+    _lib.gnmppi_rollout(dp, to_dev(prob.x_ref, "f64"), to_dev(np.zeros(prob.n), "f64"), None, 0,
+                        None, None, r0, c0)
+    _sync()
+    assert np.abs(host(r0)).max() < 1e-13
+    assert host(c0)[0] < 1e-25
+
+
+# ---------------------------------------------------------------------------
+# a3: MPPI update
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype,n,K", [("f32", 37, 1000), ("f64", 37, 1000), ("f32", 100, 4096),
+                                       ("f64", 40, 256), ("f32", 1, 1), ("f32", 3, 16384)])
+def test_mppi_update_matches_oracle(dtype, n, K):
+    rng = np.random.default_rng(n + K)
+    W = rnd(rng.standard_normal((n, K)), dtype)
+    C = rnd(rng.uniform(10.0, 14.0, K), dtype)
+    if K > 8:
+        C[3], C[5], C[7] = np.nan, np.inf, -np.inf
+    U = rnd(rng.standard_normal(n), dtype)
+    lam = 0.3
+    Ud = to_dev(U, dtype)
+    wd = to_dev(np.zeros(K), dtype)
+    st = torch.full((1,), 99, dtype=torch.int32, device=device())
+    _lib.gnmppi_mppi_update(to_dev(C, dtype), padded(W, dtype), lam, Ud, wd, st)
+    _sync()
+    assert int(st.item()) == _lib.OK
+    assert_parity(host(Ud) - U, mppi.step(W, C, lam), dtype, "dU")
+    assert_parity(host(wd), mppi.weights(C, lam), dtype, "weights")
+
+
+def test_mppi_update_all_nonfinite_leaves_U():
+    U = np.arange(5.0)
+    Ud = to_dev(U, "f32")
+    st = torch.zeros(1, dtype=torch.int32, device=device())
+    C = np.array([np.nan, np.inf, np.nan, -np.inf])
+    _lib.gnmppi_mppi_update(to_dev(C, "f32"), padded(np.ones((5, 4)), "f32"), 1.0, Ud, None, st)
+    _sync()
+    assert int(st.item()) == _lib.ENONFINITE
+    np.testing.assert_array_equal(host(Ud), U)
+
+
+# ---------------------------------------------------------------------------
+# a4: Jacobian reconstruction
+# ---------------------------------------------------------------------------
+
+def _jacobian_inputs(case):
+    if case == "c1":
+        w = wl.c1()
+        prob, x0, dtype, K, anti, sigma = w.problem, w.x0, "f64", 256, True, 0.5
+    elif case == "c2":
+        w = wl.c2()
+        prob, x0, dtype, K, anti, sigma = w.problem, w.x0, "f32", 4096, True, 0.3
+    elif case == "chain_f64_ragged":
+        prob, x0 = wl.chain_problem(n_masses=3, N=5, seed=1)
+        dtype, K, anti, sigma = "f64", 100, False, 0.2
+    elif case == "chain_f32_ragged":
+        prob, x0 = wl.chain_problem(n_masses=6, N=9, seed=2)
+        dtype, K, anti, sigma = "f32", 333, False, 0.3
+    else:
+        raise KeyError(case)
+    rp = round_problem(prob, dtype)
+    U = rnd(0.1 * np.random.default_rng(3).standard_normal(prob.n), dtype)
+    W = rnd(wl.gaussian_perturbations(prob.n, K, sigma, 21, antithetic=anti), dtype)
+    R, _ = ocp.rollout_batch(rp, rnd(x0, dtype), U, W, nominal=True)
+    R = rnd(R, dtype)  # the device receives the residuals in its own precision
+    return prob, dtype, K, sigma, R, W
+
+
+def _run_jacobian(R, W, dtype, method=_lib.JAC_LS, sigma2=0.0, ldw=None, ldr=None):
+    m, K = R.shape[0], W.shape[1]
+    n = W.shape[0]
+    Rd = padded(R[:, 1:], dtype, ld=ldr)
+    Wd = padded(W, dtype, ld=ldw)
+    r0d = to_dev(R[:, 0], dtype)
+    J = to_dev(np.zeros((m, n)), dtype)
+    code = _lib.F32 if dtype == "f32" else _lib.F64
+    work = torch.empty(_lib.gnmppi_jacobian_workspace(code, m, n, K), dtype=torch.uint8, device=device())
+    st = torch.full((1,), 99, dtype=torch.int32, device=device())
+    _lib.gnmppi_reconstruct_jacobian(Rd, r0d, Wd, J, work, method, sigma2, st, K)
+    _sync()
+    return host(J), int(st.item())
+
+
+@pytest.mark.parametrize("case", ["c1", "c2", "chain_f64_ragged", "chain_f32_ragged"])
+def test_jacobian_ls_matches_oracle(case):
+    prob, dtype, K, sigma, R, W = _jacobian_inputs(case)
+    J, st = _run_jacobian(R, W, dtype)
+    assert st == _lib.OK
+    assert_parity(J, jacobian.ls(R, W), dtype, "J (LS)")
+
+
+@pytest.mark.parametrize("case", ["c1", "chain_f32_ragged"])
+def test_jacobian_mc_matches_oracle(case):
+    prob, dtype, K, sigma, R, W = _jacobian_inputs(case)
+    J, st = _run_jacobian(R, W, dtype, _lib.JAC_MC, sigma * sigma)
+    assert st == _lib.OK
+    assert_parity(J, jacobian.mc(R, W, sigma * sigma), dtype, "J (MC)")
+
+
+def test_jacobian_unaligned_leading_dimensions_take_the_scalar_path():
+    prob, dtype, K, sigma, R, W = _jacobian_inputs("chain_f64_ragged")
+    J, st = _run_jacobian(R, W, dtype, ldw=K + 1, ldr=K + 3)
+    assert st == _lib.OK
+    assert_parity(J, jacobian.ls(R, W), dtype, "J (unaligned)")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_jacobian_at_the_largest_supported_n(dtype):
+    rng = np.random.default_rng(4)
+    n, m, K = 192, 70, 512
+    W = rnd(rng.standard_normal((n, K)), dtype)
+    A = rng.standard_normal((m, n))
+    r0 = rng.standard_normal(m)
+    R = rnd(np.concatenate([r0[:, None], r0[:, None] + A @ W], axis=1), dtype)
+    J, st = _run_jacobian(R, W, dtype)
+    assert st == _lib.OK
+    assert_parity(J, jacobian.ls(R, W), dtype, "J (n=192)")
+
+
+def test_jacobian_reports_rank_deficient_perturbations():
+    rng = np.random.default_rng(5)
+    n, K = 12, 10
+    W = rng.standard_normal((n, K))
+    R = rng.standard_normal((30, K + 1))
+    _, st = _run_jacobian(R, W, "f64")
+    assert st == _lib.ERANK
+
+
+# ---------------------------------------------------------------------------
+# a5: GGN step
+# ---------------------------------------------------------------------------
+
+def _run_ggn(J, r0, lam, dtype, inc=1):
+    m, n = J.shape
+    Jd = to_dev(J, dtype)
+    r0_full = np.zeros(m * inc)
+    r0_full[::inc] = r0
+    r0d = to_dev(r0_full, dtype)
+    dU = to_dev(np.full(n, 7.0), dtype)
+    code = _lib.F32 if dtype == "f32" else _lib.F64
+    work = torch.empty(_lib.gnmppi_ggn_workspace(code, m, n), dtype=torch.uint8, device=device())
+    st = torch.full((1,), 99, dtype=torch.int32, device=device())
+    _lib.gnmppi_ggn_step(Jd, r0d, lam, dU, work, st, inc_r0=inc)
+    _sync()
+    return host(dU), int(st.item())
+
+
+@pytest.mark.parametrize("dtype,m,n,lam,inc", [("f64", 120, 40, 0.0, 1), ("f32", 120, 40, 0.0, 1),
+                                               ("f64", 300, 37, 0.5, 3), ("f32", 3300, 100, 0.0, 1),
+                                               ("f64", 200, 192, 1e-3, 1), ("f32", 65, 1, 0.0, 2)])
+def test_ggn_step_matches_oracle(dtype, m, n, lam, inc):
+    rng = np.random.default_rng(m + n)
+    J = rnd(rng.standard_normal((m, n)) + 0.3, dtype)
+    r0 = rnd(rng.standard_normal(m), dtype)
+    dU, st = _run_ggn(J, r0, lam, dtype, inc)
+    assert st == _lib.OK
+    assert_parity(dU, ggn.direction(J, r0, lam), dtype, "dU")
+
+
+def test_ggn_step_on_the_c2_jacobian():
+    prob, dtype, K, sigma, R, W = _jacobian_inputs("c2")
+    J = rnd(jacobian.ls(R, W), dtype)
+    dU, st = _run_ggn(J, R[:, 0], 0.0, dtype)
+    assert st == _lib.OK
+    assert_parity(dU, ggn.direction(J, R[:, 0]), dtype, "dU (c2)")
+
+
+def test_ggn_step_reports_singular_normal_matrix():
+    dU, st = _run_ggn(np.zeros((20, 6)), np.ones(20), 0.0, "f64")
+    assert st == _lib.ENOTPD
+    np.testing.assert_array_equal(dU, np.zeros(6))
+
+
+# ---------------------------------------------------------------------------
+# a6: line search + apply
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case,L", [("c2", 16), ("c1", 16), ("c1", 1), ("c1", 64), ("chain5_f64", 7)])
+def test_line_search_matches_oracle(case, L):
+    if case == "c2":
+        w = wl.c2()
+        prob, x0, dtype = w.problem, w.x0, "f32"
+    elif case == "c1":
+        w = wl.c1()
+        prob, x0, dtype = w.problem, w.x0, "f64"
+    else:
+        prob, x0 = wl.chain_problem(n_masses=5, N=11, seed=9)
+        dtype = "f64"
+    rp = round_problem(prob, dtype)
+    rng = np.random.default_rng(L)
+    U = rnd(0.1 * rng.standard_normal(prob.n), dtype)
+    d = rnd(0.5 * rng.standard_normal(prob.n), dtype)
+    alphas = rnd(0.5 ** np.arange(L), dtype)
+    x0r = rnd(x0, dtype)
+    dp = DeviceProblem(prob, dtype)
+    Ud = to_dev(U, dtype)
+    Cd = to_dev(np.zeros(L), dtype)
+    info = torch.zeros(3, dtype=torch.float64, device=device())
+    _lib.gnmppi_line_search(dp, to_dev(x0r, dtype), Ud, to_dev(d, dtype), to_dev(alphas, dtype), Cd, info)
+    _sync()
+    costs_ref = ocp.cost_from_residual(ocp.residual(rp, x0r, U[:, None] + d[:, None] * alphas[None, :]))
+    costs = host(Cd)
+    assert_parity(costs, costs_ref, dtype, "candidate costs")
+    j = int(np.argmin(costs))  # the device's own decision, checked for validity
+    assert costs_ref[j] <= costs_ref.min() * (1 + 10 * TOL[dtype])
+    inf = host(info)
+    assert int(inf[2]) == j and inf[0] == alphas[j] and inf[1] == costs[j]
+    assert_parity(host(Ud), U + alphas[j] * d, dtype, "U_new")
+
+
+def test_line_search_skips_nonfinite_candidates():
+    prob, x0 = wl.chain_problem(n_masses=4, N=6, seed=1)
+    dp = DeviceProblem(prob, "f32")
+    d = np.full(prob.n, 1e30)  # large steps overflow float32
+    alphas = 2.0 ** -np.arange(0, 160, 10, dtype=np.float64)
+    Ud = to_dev(np.zeros(prob.n), "f32")
+    Cd = to_dev(np.zeros(len(alphas)), "f32")
+    info = torch.zeros(3, dtype=torch.float64, device=device())
+    _lib.gnmppi_line_search(dp, to_dev(x0, "f32"), Ud, to_dev(d, "f32"), to_dev(alphas, "f32"), Cd, info)
+    _sync()
+    costs = host(Cd)
+    assert not np.isfinite(costs[0])
+    j = int(host(info)[2])
+    assert np.isfinite(costs[j]) and costs[j] == np.nanmin(np.where(np.isfinite(costs), costs, np.nan))
+
+
+# ---------------------------------------------------------------------------
+# whole iterations (Alg. 1 and Method C)
+# ---------------------------------------------------------------------------
+
+def test_c1_gn_mppi_hits_the_riccati_optimum_in_one_iteration():
+    w = wl.c1()
+    p = w.problem
+    A, B = dynamics.double_integrator_matrices(2, p.dt)
+    Q, Rw = np.diag(p.q), np.diag(p.r)
+    Ustar, cstar = lqr.riccati_solution(A, B, Q, Rw, Q, p.N, w.x0)
+    solver = GNMPPI(DeviceProblem(p, "f64"), w.x0, w.settings, seed=1, max_iters=3)
+    solver.solve(3)
+    _sync()
+    costs, alphas, status = solver.history(3)
+    assert (status == 0).all()
+    assert abs(costs[0] - cstar) / cstar < 1e-10
+    assert abs(costs[2] - cstar) / cstar < 1e-10
+    np.testing.assert_allclose(host(solver.U), Ustar, atol=1e-9)
+    # the oracle fed the same Philox stream agrees iteration by iteration
+    noise = lambda it, s: philox.perturbations(p.n, 256, s, 1, it, "f64")  # noqa: E731
+    _, h = solvers.gn_mppi(p, w.x0, np.zeros(p.n), 3, noise, w.settings.sigma0, beta=w.settings.beta,
+                           sigma_min=w.settings.sigma_min)
+    np.testing.assert_allclose(costs, h.cost, rtol=1e-10)
+
+
+def test_c2_first_iteration_matches_oracle():
+    w = wl.c2()
+    p, st = w.problem, w.settings
+    rp = round_problem(p, "f32")
+    solver = GNMPPI(DeviceProblem(p, "f32"), w.x0, st, seed=1, max_iters=1)
+    solver.solve(1)
+    _sync()
+    costs, alphas, status = solver.history(1)
+    assert (status == 0).all()
+    noise = lambda it, s: rnd(philox.perturbations(p.n, st.K, s, 1, it, "f32"), "f32")  # noqa: E731
+    Uo, h = solvers.gn_mppi(rp, rnd(w.x0, "f32"), np.zeros(p.n), 1, noise, st.sigma0, beta=st.beta,
+                            sigma_min=st.sigma_min)
+    assert alphas[0] == h.alpha[0]
+    assert_parity([costs[0]], [h.cost[0]], "f32", "cost after one iteration")
+    assert_parity(host(solver.U), Uo, "f32", "U after one iteration", tol=1e-3)
+    assert costs[0] < ocp.cost(rp, rnd(w.x0, "f32"), np.zeros(p.n))
+
+
+def test_plain_mppi_decreases_the_cost_on_c1():
+    w = wl.c1()
+    solver = PlainMPPI(DeviceProblem(w.problem, "f64"), w.x0, w.settings, max_iters=30)
+    for it in range(30):
+        solver.step(it)
+    solver.final_cost(30)
+    _sync()
+    cost = host(solver.cost)
+    assert (host(solver.status)[:30] == 0).all()
+    assert cost[30] < 0.5 * cost[0]
