@@ -1,234 +1,318 @@
 // Dense n x n algebra of the Jacobian reconstruction (Eq. (10)) and of the
-// GGN step (Eq. (13)), all in double precision:
+// GGN step (Eq. (13)), in double precision.
 //
-//  * sweep_kernel    -- one workgroup factors an SPD matrix held as a packed
-//                       lower triangle in LDS (n <= 192: 149 KB of the 160 KB
-//                       per CU) with the symmetric sweep operator, i.e.
-//                       Gauss-Jordan elimination without pivoting, which for
-//                       an SPD matrix has the Cholesky pivots.  Sweeping
-//                       pivots 0..n-1 of [[H, g], [g^T, c]] leaves -H^{-1} in
-//                       the leading block and H^{-1} g in the last row, so
-//                       the same kernel yields G^{-1} for the LS Jacobian and
-//                       the GGN direction -(H^{-1} g) with no triangular
-//                       solves.  A pivot at or below n 2^-52 max diag marks
-//                       the matrix as not positive definite.
-//  * jac_apply_kernel -- J = S G^{-1} (LS) or J = S / (K sigma^2) (MC); it
-//                       also adds up the k-split partial sums of S.
-//  * gram_kernel     -- lower-triangular tiles of [J r0]^T [J r0] over a
-//                       chunk of rows, in double (products of float inputs
-//                       are exact in double).
+//  * reduce_sym_kernel -- adds the k-split / row-chunk partial sums of a
+//      symmetric matrix (lower triangle) into a full symmetric double matrix,
+//      one block per row so that every partial load is in flight at once.
+//  * sweep_kernel<R> -- one workgroup of 16 x 16 threads sweeps an SPD
+//      matrix with the symmetric sweep operator (Gauss-Jordan elimination
+//      without pivoting; for an SPD matrix its pivots are the Cholesky pivots
+//      squared).  Thread (ty, tx) keeps the lower-triangle elements
+//      (ty + 16 r, tx + 16 c), c <= r < R, in registers; each pivot
+//      broadcasts one column through LDS (double-buffered, so a single
+//      barrier per pivot) and every thread updates its own elements.
+//      Sweeping pivots 0..n-1 of [[H, g], [g^T, c]] leaves -H^{-1} in the
+//      leading block and H^{-1} g in the last row: the same kernel yields
+//      G^{-1} for the LS Jacobian and the GGN direction -(H^{-1} g) with no
+//      triangular solves.  A pivot at or below n 2^-52 max diag marks the
+//      matrix as not positive definite.
+//  * reduce_rows_kernel -- S (or, for MC, J = S / (K sigma^2)) as the sum of
+//      the k-split partials of the sample contraction; J = S G^{-1} then runs
+//      on the MFMA contraction kernel.
+//  * gram_kernel<NT> -- the lower tiles of [J r0]^T [J r0] over a chunk of
+//      rows with the 16x16x4 f64 MFMA (products of float inputs are exact in
+//      double); one partial sum per chunk.
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace gnm {
-
-hipError_t launch_jac_contract(int dtype, int m, int n, int rows, int K, const void* R,
-                               int64_t ldr, const void* r0, const void* W, int64_t ldw,
-                               int nsplit, int split_len, void* part, int npad, hipStream_t st);
 
 namespace {
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-__device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }  // j <= i
+using f64x4 = double __attribute__((ext_vector_type(4)));
+
+// ---- partial-sum reduction -------------------------------------------------
+
+// out (P x P, full, symmetric) = sum_sp part[sp] (rows row0.., leading dim ldp),
+// reading only entries j <= i; diag_shift is added to the first npiv diagonal
+// entries.  grid.x = P (one row each), block = 256 >= P.
+template <typename TP>
+__global__ void __launch_bounds__(256) reduce_sym_kernel(const TP* __restrict__ part, int nsplit,
+                                                         int64_t split_stride, int row0, int ldp,
+                                                         int P, int npiv, double diag_shift,
+                                                         double* __restrict__ out) {
+  const int i = blockIdx.x, j = threadIdx.x;
+  if (j > i) return;
+  const TP* src = part + static_cast<int64_t>(row0 + i) * ldp + j;
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  int sp = 0;
+  for (; sp + 4 <= nsplit; sp += 4) {
+    s0 += static_cast<double>(src[(sp + 0) * split_stride]);
+    s1 += static_cast<double>(src[(sp + 1) * split_stride]);
+    s2 += static_cast<double>(src[(sp + 2) * split_stride]);
+    s3 += static_cast<double>(src[(sp + 3) * split_stride]);
+  }
+  for (; sp < nsplit; ++sp) s0 += static_cast<double>(src[sp * split_stride]);
+  double s = (s0 + s1) + (s2 + s3);
+  if (i == j && i < npiv) s += diag_shift;
+  out[static_cast<int64_t>(i) * P + j] = s;
+  out[static_cast<int64_t>(j) * P + i] = s;
+}
+
+// ---- register-resident symmetric sweep ------------------------------------
 
 enum SweepOut { kSweepInverse = 0, kSweepDirection = 1 };
 
-// part: nsplit partial sums, each a row-major matrix with leading dimension
-// ldp, the matrix starting at row `row0`; only entries (i, j <= i) are read.
-template <typename TP, typename TO>
-__global__ void __launch_bounds__(1024) sweep_kernel(const TP* __restrict__ part, int nsplit,
-                                                     int64_t split_stride, int row0, int ldp,
-                                                     int P, int npiv, double diag_shift, int mode,
-                                                     double* __restrict__ inv_out,
-                                                     TO* __restrict__ dir_out,
-                                                     int32_t* status, int fail_code) {
-  __shared__ double A[kMaxSweepDim * (kMaxSweepDim + 1) / 2];
-  __shared__ double colv[kMaxSweepDim];
+// Reciprocal of an FP64 pivot: the hardware estimate refined by two
+// Newton-Raphson steps x <- x + x (1 - d x) (quadratic convergence; the
+// result is within an ulp of 1/d).
+__device__ __forceinline__ double recip(double d) {
+  double x = __builtin_amdgcn_rcp(d);
+  x = fma(fma(-d, x, 1.0), x, x);
+  x = fma(fma(-d, x, 1.0), x, x);
+  return x;
+}
+
+// One pivot p = 16 PB + pm of the sweep, written as a single rank-1 update:
+// with c = column p, d = c_p and z = c - (d + 1) e_p (c with its pivot entry
+// replaced by -1), the swept matrix is A_{\p} - z z^T / d, where A_{\p} is A
+// with row and column p set to zero.  PB is a compile-time column block, so
+// every register index is static and only the PB row / column blocks need a
+// select.
+template <int R, int PB>
+__device__ __forceinline__ bool sweep_pivot(double (&A)[R][R], double* __restrict__ cv, int P,
+                                            int pm, int tx, int ty, double tol) {
+  const int p = 16 * PB + pm;
+  const bool col_owner = tx == pm, row_owner = ty == pm;
+  // publish column p: rows >= 16 PB from column block PB, rows < 16 PB from row p
+  if (col_owner) {
+#pragma unroll
+    for (int r = PB; r < R; ++r) {
+      const int i = ty + 16 * r;
+      if (i < P) cv[i] = A[r][PB];
+    }
+  }
+  if (row_owner) {
+#pragma unroll
+    for (int c = 0; c < PB; ++c) cv[tx + 16 * c] = A[PB][c];
+  }
+  __syncthreads();
+  const double d = cv[p];
+  if (!(d > tol)) return false;  // the same pivot in every thread: uniform
+  const double inv = recip(d);
+  double zi[R], zj[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = ty + 16 * r, j = tx + 16 * r;
+    zi[r] = i < P ? cv[i] : 0.0;
+    zj[r] = j < P ? cv[j] : 0.0;
+  }
+  if (row_owner) zi[PB] = -1.0;
+  if (col_owner) zj[PB] = -1.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double sr = -zi[r] * inv;
+#pragma unroll
+    for (int c = 0; c <= r; ++c) {
+      double a = A[r][c];
+      if (r == PB && row_owner) a = 0.0;
+      if (c == PB && col_owner) a = 0.0;
+      A[r][c] = fma(sr, zj[c], a);
+    }
+  }
+  return true;
+}
+
+template <int R, int PB>
+__device__ __forceinline__ bool sweep_block(double (&A)[R][R], double (*colv)[16 * R], int P,
+                                            int npiv, int tx, int ty, double tol) {
+  if constexpr (PB < R) {
+    const int pend = min(16, npiv - 16 * PB);
+    for (int pm = 0; pm < pend; ++pm)
+      if (!sweep_pivot<R, PB>(A, colv[(16 * PB + pm) & 1], P, pm, tx, ty, tol)) return false;
+    if (16 * (PB + 1) < npiv) return sweep_block<R, PB + 1>(A, colv, P, npiv, tx, ty, tol);
+  }
+  return true;
+}
+
+template <int R, typename TO>
+__global__ void __launch_bounds__(256) sweep_kernel(const double* __restrict__ M, int P, int npiv,
+                                                    int mode, TO* __restrict__ inv_out,
+                                                    int64_t ldo, TO* __restrict__ dir_out,
+                                                    int32_t* status, int fail_code) {
+  __shared__ double colv[2][16 * R];
   __shared__ double tol_s;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const int nty = blockDim.x >> 5;
-  for (int i = ty; i < P; i += nty)
-    for (int j = tx; j <= i; j += 32) {
-      double s = 0;
-      for (int sp = 0; sp < nsplit; ++sp)
-        s += static_cast<double>(part[sp * split_stride + static_cast<int64_t>(row0 + i) * ldp + j]);
-      if (i == j && i < npiv) s += diag_shift;
-      A[tri(i, j)] = s;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double A[R][R];  // only c <= r is used
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c <= r; ++c) {
+      const int i = ty + 16 * r, j = tx + 16 * c;
+      A[r][c] = (i < P && j < P) ? M[static_cast<int64_t>(i) * P + j] : 0.0;
     }
+  // pivot threshold from the largest diagonal entry, reduced from registers
+  double dmax = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (tx == ty && ty + 16 * r < npiv) dmax = fmax(dmax, A[r][r]);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off, kWave));
+  if ((threadIdx.x & 63) == 0) colv[0][threadIdx.x >> 6] = dmax;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double mx = 0;
-    for (int i = 0; i < npiv; ++i) mx = fmax(mx, A[tri(i, i)]);
-    tol_s = static_cast<double>(npiv) * 0x1.0p-52 * mx;
-  }
+  if (threadIdx.x == 0)
+    tol_s = static_cast<double>(npiv) * 0x1.0p-52 *
+            fmax(fmax(colv[0][0], colv[0][1]), fmax(colv[0][2], colv[0][3]));
   __syncthreads();
-  const double tol = tol_s;
-  bool ok = true;
-  for (int p = 0; p < npiv; ++p) {
-    for (int i = threadIdx.x; i < P; i += blockDim.x) colv[i] = i >= p ? A[tri(i, p)] : A[tri(p, i)];
-    __syncthreads();
-    const double d = colv[p];
-    if (!(d > tol)) {  // every thread reads the same pivot: uniform exit
-      ok = false;
-      break;
-    }
-    const double inv = 1.0 / d;
-    for (int i = ty; i < P; i += nty)
-      for (int j = tx; j <= i; j += 32) {
-        double v;
-        if (i == p && j == p)
-          v = -inv;
-        else if (i == p)
-          v = colv[j] * inv;
-        else if (j == p)
-          v = colv[i] * inv;
-        else
-          v = A[tri(i, j)] - colv[i] * colv[j] * inv;
-        A[tri(i, j)] = v;
-      }
-    __syncthreads();
-  }
+  const bool ok = sweep_block<R, 0>(A, colv, P, npiv, tx, ty, tol_s);
   if (mode == kSweepInverse) {
     if (ok)
-      for (int i = ty; i < npiv; i += nty)
-        for (int j = tx; j < npiv; j += 32)
-          inv_out[i * npiv + j] = -(j <= i ? A[tri(i, j)] : A[tri(j, i)]);
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c <= r; ++c) {
+          const int i = ty + 16 * r, j = tx + 16 * c;
+          if (i < npiv && j <= i) {
+            inv_out[i * ldo + j] = static_cast<TO>(-A[r][c]);
+            inv_out[j * ldo + i] = static_cast<TO>(-A[r][c]);
+          }
+        }
   } else {
-    for (int j = threadIdx.x; j < npiv; j += blockDim.x)
-      dir_out[j] = ok ? static_cast<TO>(-A[tri(npiv, j)]) : TO(0);
+    // the augmented row npiv holds H^{-1} g in columns j < npiv
+    const int rb = npiv >> 4, rm = npiv & 15;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (r == rb && ty == rm)
+#pragma unroll
+        for (int c = 0; c <= r; ++c) {
+          const int j = tx + 16 * c;
+          if (j < npiv) dir_out[j] = ok ? static_cast<TO>(-A[r][c]) : TO(0);
+        }
   }
   if (threadIdx.x == 0 && status) *status = ok ? GNMPPI_OK : fail_code;
 }
 
-// J rows [32 b, 32 b + 32): S summed over the k-split partials, then
-// multiplied by G^{-1} (LS) or scaled (MC).
-constexpr int kApplyRows = 32;
-constexpr int kMaxN = 192;
-
-template <typename T>
-__global__ void __launch_bounds__(256) jac_apply_kernel(int m, int n, const T* __restrict__ part,
-                                                        int nsplit, int64_t split_stride, int npad,
-                                                        const double* __restrict__ Ginv,
-                                                        double mc_scale, int method,
-                                                        T* __restrict__ J, int64_t ldj) {
-  __shared__ double Ss[kApplyRows][kMaxN + 1];
-  const int i0 = blockIdx.x * kApplyRows;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kApplyRows * n; e += blockDim.x) {
-    const int r = e / n, c = e - r * n;
-    const int i = i0 + r;
-    double s = 0;
-    if (i < m)
-      for (int sp = 0; sp < nsplit; ++sp)
-        s += static_cast<double>(part[sp * split_stride + static_cast<int64_t>(i) * npad + c]);
-    Ss[r][c] = s;
+template <typename TO>
+hipError_t launch_sweep(int P, int npiv, int mode, const double* M, TO* inv_out, int64_t ldo,
+                        TO* dir_out, int32_t* status, int fail_code, hipStream_t st) {
+  const int R = (P + 15) / 16;
+#define GNM_SWEEP_CASE(RR)                                                                      \
+  case RR:                                                                                      \
+    hipLaunchKernelGGL((sweep_kernel<RR, TO>), dim3(1), dim3(256), 0, st, M, P, npiv, mode,     \
+                       inv_out, ldo, dir_out, status, fail_code);                               \
+    break;
+  switch (R) {
+    GNM_SWEEP_CASE(1) GNM_SWEEP_CASE(2) GNM_SWEEP_CASE(3) GNM_SWEEP_CASE(4) GNM_SWEEP_CASE(5)
+    GNM_SWEEP_CASE(6) GNM_SWEEP_CASE(7) GNM_SWEEP_CASE(8) GNM_SWEEP_CASE(9) GNM_SWEEP_CASE(10)
+    GNM_SWEEP_CASE(11) GNM_SWEEP_CASE(12) GNM_SWEEP_CASE(13)
+    default:
+      return hipErrorInvalidValue;
   }
-  __syncthreads();
-  if (method == GNMPPI_JAC_MC) {
-    for (int e = tid; e < kApplyRows * n; e += blockDim.x) {
-      const int r = e / n, c = e - r * n;
-      if (i0 + r < m) J[static_cast<int64_t>(i0 + r) * ldj + c] = static_cast<T>(Ss[r][c] * mc_scale);
-    }
-    return;
-  }
-  const int tx = tid & 31, ty = tid >> 5;  // columns tx + 32 q, rows ty + 8 p
-  constexpr int QN = kMaxN / 32, PR = kApplyRows / 8;
-  double acc[PR][QN];
-#pragma unroll
-  for (int p = 0; p < PR; ++p)
-#pragma unroll
-    for (int q = 0; q < QN; ++q) acc[p][q] = 0;
-  for (int k = 0; k < n; ++k) {
-    double g[QN];
-#pragma unroll
-    for (int q = 0; q < QN; ++q) {
-      const int c = tx + 32 * q;
-      g[q] = c < n ? Ginv[k * n + c] : 0.0;
-    }
-#pragma unroll
-    for (int p = 0; p < PR; ++p) {
-      const double s = Ss[ty + 8 * p][k];
-#pragma unroll
-      for (int q = 0; q < QN; ++q) acc[p][q] += s * g[q];
-    }
-  }
-#pragma unroll
-  for (int p = 0; p < PR; ++p) {
-    const int i = i0 + ty + 8 * p;
-    if (i >= m) continue;
-#pragma unroll
-    for (int q = 0; q < QN; ++q) {
-      const int c = tx + 32 * q;
-      if (c < n) J[static_cast<int64_t>(i) * ldj + c] = static_cast<T>(acc[p][q]);
-    }
-  }
+#undef GNM_SWEEP_CASE
+  return hipGetLastError();
 }
 
-// Lower-triangular 64x64 tiles of X^T X with X = [J r0] (m x (n+1)), over the
-// rows of one chunk.  grid.x enumerates tile pairs (ta >= tb), grid.y chunks.
-constexpr int kGramTile = 64;
-constexpr int kGramSub = 32;
+// ---- S = sum of the k-split partials ------------------------------------------
 
+// out[i, c] = scale * sum_sp part[sp][i, c] for i < m, c < n: 4 rows x 64
+// columns per block, one element per thread, all partial loads in flight.
 template <typename T>
+__global__ void __launch_bounds__(256) reduce_rows_kernel(const T* __restrict__ part, int nsplit,
+                                                          int64_t split_stride, int ldp, int m,
+                                                          int n, double scale, T* __restrict__ out,
+                                                          int64_t ldo) {
+  const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  if (i >= m || c >= n) return;
+  const T* src = part + static_cast<int64_t>(i) * ldp + c;
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  int sp = 0;
+  for (; sp + 4 <= nsplit; sp += 4) {
+    s0 += static_cast<double>(src[(sp + 0) * split_stride]);
+    s1 += static_cast<double>(src[(sp + 1) * split_stride]);
+    s2 += static_cast<double>(src[(sp + 2) * split_stride]);
+    s3 += static_cast<double>(src[(sp + 3) * split_stride]);
+  }
+  for (; sp < nsplit; ++sp) s0 += static_cast<double>(src[sp * split_stride]);
+  out[i * ldo + c] = static_cast<T>(((s0 + s1) + (s2 + s3)) * scale);
+}
+
+// ---- [J r0]^T [J r0] with the f64 MFMA ------------------------------------------
+
+// f64 16x16x4 MFMA: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+// accumulator element j of lane l is D[4 j + l / 16][l % 16].
+template <typename T, int NT>
 __global__ void __launch_bounds__(256) gram_kernel(int m, int n, const T* __restrict__ J,
                                                    int64_t ldj, const T* __restrict__ r0,
-                                                   int64_t inc, int chunk,
-                                                   double* __restrict__ part, int P) {
-  __shared__ double Xa[kGramSub][kGramTile + 1];
-  __shared__ double Xb[kGramSub][kGramTile + 1];
-  int ta = 0, rem = blockIdx.x;
-  while (rem > ta) {
-    rem -= ta + 1;
-    ++ta;
-  }
-  const int tb = rem;
-  const int a0 = ta * kGramTile, b0 = tb * kGramTile;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  const int ibeg = blockIdx.y * chunk, iend = min(m, ibeg + chunk);
-  double acc[4][4];
+                                                   int64_t inc, int chunk, int P,
+                                                   double* __restrict__ part) {
+  constexpr int NPAIR = NT * (NT + 1) / 2;
+  constexpr int NACC = (NPAIR + 3) / 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const int ibeg = blockIdx.x * chunk, iend = min(m, ibeg + chunk);
+  f64x4 acc[NACC];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int q = 0; q < NACC; ++q) acc[q] = f64x4{0, 0, 0, 0};
+  for (int k0 = ibeg; k0 < iend; k0 += 4) {
+    const int row = k0 + kq;
+    const bool rv = row < iend;
+    double x[NT];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0;
-  auto xval = [&](int i, int c) -> double {
-    if (i >= iend || c > n) return 0.0;
-    return c < n ? static_cast<double>(J[static_cast<int64_t>(i) * ldj + c])
-                 : static_cast<double>(r0[static_cast<int64_t>(i) * inc]);
-  };
-  for (int s0 = ibeg; s0 < iend; s0 += kGramSub) {
-    for (int e = tid; e < kGramSub * kGramTile; e += blockDim.x) {
-      const int rr = e / kGramTile, cc = e - rr * kGramTile;
-      Xa[rr][cc] = xval(s0 + rr, a0 + cc);
-      Xb[rr][cc] = xval(s0 + rr, b0 + cc);
+    for (int t = 0; t < NT; ++t) {
+      const int col = 16 * t + r16;
+      double v = 0.0;
+      if (rv) {
+        if (col < n)
+          v = static_cast<double>(J[static_cast<int64_t>(row) * ldj + col]);
+        else if (col == n)
+          v = static_cast<double>(r0[static_cast<int64_t>(row) * inc]);
+      }
+      x[t] = v;
     }
-    __syncthreads();
-#pragma unroll 4
-    for (int rr = 0; rr < kGramSub; ++rr) {
-      double xa[4], xb[4];
+    int q = 0;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) xa[u] = Xa[rr][ty + 16 * u];
+    for (int ta = 0; ta < NT; ++ta)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) xb[v] = Xb[rr][tx + 16 * v];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += xa[u] * xb[v];
-    }
-    __syncthreads();
+      for (int tb = 0; tb <= ta; ++tb, ++q)
+        if ((q & 3) == wave)
+          acc[q >> 2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[ta], x[tb], acc[q >> 2], 0, 0, 0);
   }
-  double* out = part + static_cast<int64_t>(blockIdx.y) * P * P;
+  double* out = part + static_cast<int64_t>(blockIdx.x) * P * P;
+  int q = 0;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int a = a0 + ty + 16 * u;
-    if (a >= P) continue;
+  for (int ta = 0; ta < NT; ++ta)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int b = b0 + tx + 16 * v;
-      if (b < P && b <= a) out[static_cast<int64_t>(a) * P + b] = acc[u][v];
-    }
+    for (int tb = 0; tb <= ta; ++tb, ++q)
+      if ((q & 3) == wave) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int a = 16 * ta + 4 * j + kq, b = 16 * tb + r16;
+          if (a < P && b < P) out[static_cast<int64_t>(a) * P + b] = acc[q >> 2][j];
+        }
+      }
+}
+
+template <typename T>
+hipError_t launch_gram(int nt, int nblocks, hipStream_t st, int m, int n, const T* J, int64_t ldj,
+                       const T* r0, int64_t inc, int chunk, int P, double* part) {
+#define GNM_GRAM_CASE(NT)                                                                     \
+  case NT:                                                                                    \
+    hipLaunchKernelGGL((gram_kernel<T, NT>), dim3(nblocks), dim3(256), 0, st, m, n, J, ldj, r0, \
+                       inc, chunk, P, part);                                                  \
+    break;
+  switch (nt) {
+    GNM_GRAM_CASE(1) GNM_GRAM_CASE(2) GNM_GRAM_CASE(3) GNM_GRAM_CASE(4) GNM_GRAM_CASE(5)
+    GNM_GRAM_CASE(6) GNM_GRAM_CASE(7) GNM_GRAM_CASE(8) GNM_GRAM_CASE(9) GNM_GRAM_CASE(10)
+    GNM_GRAM_CASE(11) GNM_GRAM_CASE(12) GNM_GRAM_CASE(13)
+    default:
+      return hipErrorInvalidValue;
   }
+#undef GNM_GRAM_CASE
+  return hipGetLastError();
 }
 
 __global__ void set_status_kernel(int32_t* status, int32_t value) { *status = value; }
@@ -252,68 +336,84 @@ JacPlan jacobian_plan(int dtype, int m, int n, int K, int method) {
   p.nsplit = (ksteps + steps_per_split - 1) / steps_per_split;
   p.split_len = steps_per_split * step;
   p.part_bytes = align_up(static_cast<size_t>(p.nsplit) * p.rows * p.npad * esz);
-  p.ginv_off = p.part_bytes;
-  p.total = p.part_bytes + align_up(static_cast<size_t>(n) * n * 8);
+  p.gsum_off = p.part_bytes;
+  p.ginv_off = p.gsum_off + align_up(static_cast<size_t>(n) * n * 8);
+  p.s_off = p.ginv_off + align_up(static_cast<size_t>(n) * p.npad * esz);
+  p.total = p.s_off + align_up(static_cast<size_t>(m) * p.npad * esz);
   return p;
+}
+
+template <typename T>
+hipError_t jacobian_typed(int m, int n, int K, const T* R, int64_t ldr, const T* r0, const T* W,
+                          int64_t ldw, int method, double sigma2, T* J, int64_t ldj, void* work,
+                          int32_t* status, hipStream_t st) {
+  const int dtype = sizeof(T) == 4 ? GNMPPI_F32 : GNMPPI_F64;
+  const JacPlan pl = jacobian_plan(dtype, m, n, K, method);
+  char* wk = static_cast<char*>(work);
+  T* part = reinterpret_cast<T*>(wk);
+  const int64_t split_stride = static_cast<int64_t>(pl.rows) * pl.npad;
+  // S = (R - r0 1^T) W^T and (LS) G = W W^T, as k-split partial sums
+  ContractArgs<T> c1{m, pl.rows, n, K, R, ldr, r0, W, ldw, W, ldw, pl.split_len,
+                     part, pl.npad, split_stride, pl.npad};
+  hipError_t e = launch_contract(c1, pl.nsplit, st);
+  if (e != hipSuccess) return e;
+  const dim3 rgrid((n + 63) / 64, (m + 3) / 4);
+  if (method == GNMPPI_JAC_MC) {
+    hipLaunchKernelGGL(reduce_rows_kernel<T>, rgrid, dim3(256), 0, st, part, pl.nsplit,
+                       split_stride, pl.npad, m, n, 1.0 / (static_cast<double>(K) * sigma2), J,
+                       ldj);
+    e = hipGetLastError();
+    if (e == hipSuccess && status) {
+      // MC has no factorisation that can fail; report success in stream order.
+      hipLaunchKernelGGL(set_status_kernel, dim3(1), dim3(1), 0, st, status, GNMPPI_OK);
+      e = hipGetLastError();
+    }
+    return e;
+  }
+  double* Gsum = reinterpret_cast<double*>(wk + pl.gsum_off);
+  T* Ginv = reinterpret_cast<T*>(wk + pl.ginv_off);
+  T* S = reinterpret_cast<T*>(wk + pl.s_off);
+  hipLaunchKernelGGL(reduce_sym_kernel<T>, dim3(n), dim3(256), 0, st, part, pl.nsplit,
+                     split_stride, m, pl.npad, n, n, 0.0, Gsum);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_sweep<T>(n, n, kSweepInverse, Gsum, Ginv, pl.npad, nullptr, status, GNMPPI_ERANK, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reduce_rows_kernel<T>, rgrid, dim3(256), 0, st, part, pl.nsplit, split_stride,
+                     pl.npad, m, n, 1.0, S, pl.npad);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // J = S G^{-1} = S (G^{-1})^T: the same contraction over the decision index
+  ContractArgs<T> c2{m, m, n, n, S, pl.npad, nullptr, nullptr, 0, Ginv, pl.npad, n,
+                     J, ldj, 0, n};
+  return launch_contract(c2, 1, st);
 }
 
 hipError_t launch_jacobian(int dtype, int m, int n, int K, const void* R, int64_t ldr,
                            const void* r0, const void* W, int64_t ldw, int method, double sigma2,
                            void* J, int64_t ldj, void* work, int32_t* status, hipStream_t st) {
-  const JacPlan pl = jacobian_plan(dtype, m, n, K, method);
-  char* wk = static_cast<char*>(work);
-  hipError_t e = launch_jac_contract(dtype, m, n, pl.rows, K, R, ldr, r0, W, ldw, pl.nsplit,
-                                     pl.split_len, wk, pl.npad, st);
-  if (e != hipSuccess) return e;
-  const int64_t split_stride = static_cast<int64_t>(pl.rows) * pl.npad;
-  double* Ginv = reinterpret_cast<double*>(wk + pl.ginv_off);
-  if (method == GNMPPI_JAC_LS) {
-    if (dtype == GNMPPI_F32)
-      hipLaunchKernelGGL((sweep_kernel<float, float>), dim3(1), dim3(1024), 0, st,
-                         reinterpret_cast<const float*>(wk), pl.nsplit, split_stride, m, pl.npad,
-                         n, n, 0.0, static_cast<int>(kSweepInverse), Ginv,
-                         static_cast<float*>(nullptr), status, GNMPPI_ERANK);
-    else
-      hipLaunchKernelGGL((sweep_kernel<double, double>), dim3(1), dim3(1024), 0, st,
-                         reinterpret_cast<const double*>(wk), pl.nsplit, split_stride, m, pl.npad,
-                         n, n, 0.0, static_cast<int>(kSweepInverse), Ginv,
-                         static_cast<double*>(nullptr), status, GNMPPI_ERANK);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  const double mc_scale = 1.0 / (static_cast<double>(K) * sigma2);
-  dim3 grid((m + kApplyRows - 1) / kApplyRows);
   if (dtype == GNMPPI_F32)
-    hipLaunchKernelGGL(jac_apply_kernel<float>, grid, dim3(256), 0, st, m, n,
-                       reinterpret_cast<const float*>(wk), pl.nsplit, split_stride, pl.npad,
-                       Ginv, mc_scale, method, static_cast<float*>(J), ldj);
-  else
-    hipLaunchKernelGGL(jac_apply_kernel<double>, grid, dim3(256), 0, st, m, n,
-                       reinterpret_cast<const double*>(wk), pl.nsplit, split_stride, pl.npad,
-                       Ginv, mc_scale, method, static_cast<double*>(J), ldj);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (method == GNMPPI_JAC_MC && status) {
-    // MC has no factorisation that can fail; report success in stream order.
-    hipLaunchKernelGGL(set_status_kernel, dim3(1), dim3(1), 0, st, status, GNMPPI_OK);
-    e = hipGetLastError();
-  }
-  return e;
+    return jacobian_typed<float>(m, n, K, static_cast<const float*>(R), ldr,
+                                 static_cast<const float*>(r0), static_cast<const float*>(W), ldw,
+                                 method, sigma2, static_cast<float*>(J), ldj, work, status, st);
+  return jacobian_typed<double>(m, n, K, static_cast<const double*>(R), ldr,
+                                static_cast<const double*>(r0), static_cast<const double*>(W), ldw,
+                                method, sigma2, static_cast<double*>(J), ldj, work, status, st);
 }
 
 GgnPlan ggn_plan(int dtype, int m, int n) {
   (void)dtype;
   GgnPlan g{};
   g.P = n + 1;
-  g.tiles = (g.P + kGramTile - 1) / kGramTile;
-  const int pairs = g.tiles * (g.tiles + 1) / 2;
-  int nsplit = (128 + pairs - 1) / pairs;
-  if (nsplit > 24) nsplit = 24;
+  g.tiles = (g.P + 15) / 16;
+  int nsplit = (m + 31) / 32;  // ~32 rows (8 MFMA k-steps) per block at least
+  if (nsplit > 96) nsplit = 96;
   int chunk = (m + nsplit - 1) / nsplit;
-  chunk = (chunk + kGramSub - 1) / kGramSub * kGramSub;
+  chunk = (chunk + 3) / 4 * 4;
   g.chunk = chunk;
   g.nsplit = (m + chunk - 1) / chunk;
-  g.total = align_up(static_cast<size_t>(g.nsplit) * g.P * g.P * 8);
+  g.part_bytes = align_up(static_cast<size_t>(g.nsplit) * g.P * g.P * 8);
+  g.total = g.part_bytes + align_up(static_cast<size_t>(g.P) * g.P * 8);
   return g;
 }
 
@@ -322,30 +422,25 @@ hipError_t launch_ggn(int dtype, int m, int n, const void* J, int64_t ldj, const
                       hipStream_t st) {
   const GgnPlan g = ggn_plan(dtype, m, n);
   double* part = static_cast<double*>(work);
-  const int pairs = g.tiles * (g.tiles + 1) / 2;
-  dim3 grid(pairs, g.nsplit);
+  double* Hsum = reinterpret_cast<double*>(static_cast<char*>(work) + g.part_bytes);
+  hipError_t e;
   if (dtype == GNMPPI_F32)
-    hipLaunchKernelGGL(gram_kernel<float>, grid, dim3(256), 0, st, m, n,
-                       static_cast<const float*>(J), ldj, static_cast<const float*>(r0), inc_r0,
-                       g.chunk, part, g.P);
+    e = launch_gram<float>(g.tiles, g.nsplit, st, m, n, static_cast<const float*>(J), ldj,
+                           static_cast<const float*>(r0), inc_r0, g.chunk, g.P, part);
   else
-    hipLaunchKernelGGL(gram_kernel<double>, grid, dim3(256), 0, st, m, n,
-                       static_cast<const double*>(J), ldj, static_cast<const double*>(r0),
-                       inc_r0, g.chunk, part, g.P);
-  hipError_t e = hipGetLastError();
+    e = launch_gram<double>(g.tiles, g.nsplit, st, m, n, static_cast<const double*>(J), ldj,
+                            static_cast<const double*>(r0), inc_r0, g.chunk, g.P, part);
   if (e != hipSuccess) return e;
   const int64_t split_stride = static_cast<int64_t>(g.P) * g.P;
+  hipLaunchKernelGGL(reduce_sym_kernel<double>, dim3(g.P), dim3(256), 0, st, part, g.nsplit,
+                     split_stride, 0, g.P, g.P, n, lm_lambda, Hsum);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
   if (dtype == GNMPPI_F32)
-    hipLaunchKernelGGL((sweep_kernel<double, float>), dim3(1), dim3(1024), 0, st, part, g.nsplit,
-                       split_stride, 0, g.P, g.P, n, lm_lambda, static_cast<int>(kSweepDirection),
-                       static_cast<double*>(nullptr), static_cast<float*>(dU), status,
-                       GNMPPI_ENOTPD);
-  else
-    hipLaunchKernelGGL((sweep_kernel<double, double>), dim3(1), dim3(1024), 0, st, part,
-                       g.nsplit, split_stride, 0, g.P, g.P, n, lm_lambda,
-                       static_cast<int>(kSweepDirection), static_cast<double*>(nullptr),
-                       static_cast<double*>(dU), status, GNMPPI_ENOTPD);
-  return hipGetLastError();
+    return launch_sweep<float>(g.P, n, kSweepDirection, Hsum, nullptr, 0, static_cast<float*>(dU),
+                               status, GNMPPI_ENOTPD, st);
+  return launch_sweep<double>(g.P, n, kSweepDirection, Hsum, nullptr, 0, static_cast<double*>(dU),
+                              status, GNMPPI_ENOTPD, st);
 }
 
 }  // namespace gnm

@@ -1,5 +1,7 @@
-// Contractions over the sample index for the Jacobian reconstruction of
-// Eq. (10):  S = (R - r0 1^T) W^T  (m x n)  and  G = W W^T  (n x n).
+// Contractions of the form  out = A B^T  with the contraction index
+// contiguous in both operands, on MFMA.  The Jacobian reconstruction of
+// Eq. (10) uses it twice: S = (R - r0 1^T) W^T and G = W W^T over the sample
+// index, then J = S G^{-1} over the decision index (G^{-1} is symmetric).
 //
 // Both operands are sample-fastest, so the contraction index is the
 // contiguous one for A and for B ("A B^T" form): each lane streams 16-byte
@@ -74,43 +76,40 @@ __device__ __forceinline__ void load_lane_k(const T* __restrict__ p, int kl, int
 }
 
 template <typename T, int TM, int NT, bool VEC>
-__global__ void __launch_bounds__(256) jac_contract_kernel(
-    int m, int n, int rows, int K, const T* __restrict__ R, int64_t ldr, const T* __restrict__ r0,
-    const T* __restrict__ W, int64_t ldw, int split_len, T* __restrict__ part, int npad) {
+__global__ void __launch_bounds__(256) contract_kernel(ContractArgs<T> a) {
   using MT = Mfma<T>;
   using Acc = typename MT::Acc;
   constexpr int V = MT::kLaneK, STEP = MT::kStep;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int r16 = lane & 15, kq = lane >> 4;
   const int row_base = (blockIdx.x * 4 + wave) * 16 * TM;
-  const int kbeg = blockIdx.y * split_len;
-  const int kend = min(K, kbeg + split_len);
+  const int kbeg = blockIdx.y * a.split_len;
+  const int kend = min(a.K, kbeg + a.split_len);
 
   const T* arow[TM];
   T asub[TM];
 #pragma unroll
   for (int tm = 0; tm < TM; ++tm) {
     const int row = row_base + 16 * tm + r16;
-    if (row < m) {
-      arow[tm] = R + row * ldr;
-      asub[tm] = r0[row];
-    } else if (row < rows) {
-      arow[tm] = W + (row - m) * ldw;
+    if (row < a.m) {
+      arow[tm] = a.A + row * a.lda;
+      asub[tm] = a.asub ? a.asub[row] : T(0);
+    } else if (row < a.rows) {
+      arow[tm] = a.A2 + (row - a.m) * a.lda2;
       asub[tm] = 0;
     } else {  // past the last row: read a valid row, never stored
-      arow[tm] = W;
+      arow[tm] = a.B;
       asub[tm] = 0;
     }
   }
   const T* bcol[NT];
+  bool bzero[NT];
 #pragma unroll
   for (int tn = 0; tn < NT; ++tn) {
     const int col = 16 * tn + r16;
-    bcol[tn] = W + (col < n ? col : 0) * ldw;
+    bcol[tn] = a.B + (col < a.ncol ? col : 0) * a.ldb;
+    bzero[tn] = col >= a.ncol;
   }
-  bool bzero[NT];
-#pragma unroll
-  for (int tn = 0; tn < NT; ++tn) bzero[tn] = (16 * tn + r16) >= n;
 
   Acc acc[TM][NT];
 #pragma unroll
@@ -118,53 +117,53 @@ __global__ void __launch_bounds__(256) jac_contract_kernel(
 #pragma unroll
     for (int tn = 0; tn < NT; ++tn) acc[tm][tn] = Acc{0, 0, 0, 0};
 
-  if (row_base < rows) {
+  if (row_base < a.rows) {
     for (int k0 = kbeg; k0 < kend; k0 += STEP) {
       const bool full = k0 + STEP <= kend;
       const int kl = k0 + kq * V;
-      T a[TM][V], b[NT][V];
+      T av[TM][V], bv[NT][V];
 #pragma unroll
       for (int tm = 0; tm < TM; ++tm) {
-        load_lane_k<T, VEC>(arow[tm], kl, kend, full, a[tm]);
+        load_lane_k<T, VEC>(arow[tm], kl, kend, full, av[tm]);
 #pragma unroll
-        for (int t = 0; t < V; ++t) a[tm][t] = (kl + t < kend) ? a[tm][t] - asub[tm] : T(0);
+        for (int t = 0; t < V; ++t) av[tm][t] = (kl + t < kend) ? av[tm][t] - asub[tm] : T(0);
       }
 #pragma unroll
       for (int tn = 0; tn < NT; ++tn) {
-        load_lane_k<T, VEC>(bcol[tn], kl, kend, full, b[tn]);
+        load_lane_k<T, VEC>(bcol[tn], kl, kend, full, bv[tn]);
         if (bzero[tn])
 #pragma unroll
-          for (int t = 0; t < V; ++t) b[tn][t] = 0;
+          for (int t = 0; t < V; ++t) bv[tn][t] = 0;
       }
 #pragma unroll
       for (int t = 0; t < V; ++t)
 #pragma unroll
         for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
-          for (int tn = 0; tn < NT; ++tn) acc[tm][tn] = MT::mma(a[tm][t], b[tn][t], acc[tm][tn]);
+          for (int tn = 0; tn < NT; ++tn) acc[tm][tn] = MT::mma(av[tm][t], bv[tn][t], acc[tm][tn]);
     }
   }
 
-  T* out = part + static_cast<int64_t>(blockIdx.y) * rows * npad;
+  T* out = a.out + static_cast<int64_t>(blockIdx.y) * a.split_stride;
 #pragma unroll
   for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int row = row_base + 16 * tm + MT::out_row(kq, j);
-      if (row < rows)
+      if (row < a.rows)
 #pragma unroll
-        for (int tn = 0; tn < NT; ++tn) out[row * npad + 16 * tn + r16] = acc[tm][tn][j];
+        for (int tn = 0; tn < NT; ++tn) {
+          const int col = 16 * tn + r16;
+          if (col < a.ocols) out[row * a.ldo + col] = acc[tm][tn][j];
+        }
     }
 }
 
 template <typename T, int TM, bool VEC>
-hipError_t contract_dispatch_nt(int nt, dim3 grid, hipStream_t st, int m, int n, int rows, int K,
-                                const T* R, int64_t ldr, const T* r0, const T* W, int64_t ldw,
-                                int split_len, T* part, int npad) {
-#define GNM_NT_CASE(NT)                                                                           \
-  case NT:                                                                                        \
-    hipLaunchKernelGGL((jac_contract_kernel<T, TM, NT, VEC>), grid, dim3(256), 0, st, m, n, rows, \
-                       K, R, ldr, r0, W, ldw, split_len, part, npad);                             \
+hipError_t contract_dispatch_nt(int nt, dim3 grid, hipStream_t st, const ContractArgs<T>& a) {
+#define GNM_NT_CASE(NT)                                                                       \
+  case NT:                                                                                    \
+    hipLaunchKernelGGL((contract_kernel<T, TM, NT, VEC>), grid, dim3(256), 0, st, a);         \
     break;
   switch (nt) {
     GNM_NT_CASE(1) GNM_NT_CASE(2) GNM_NT_CASE(3) GNM_NT_CASE(4) GNM_NT_CASE(5) GNM_NT_CASE(6)
@@ -176,42 +175,30 @@ hipError_t contract_dispatch_nt(int nt, dim3 grid, hipStream_t st, int m, int n,
   return hipGetLastError();
 }
 
+template <typename T>
+bool vec_ok(const T* p, int64_t ld) {
+  constexpr int per = 16 / sizeof(T);
+  return p == nullptr || ((ld % per) == 0 && (reinterpret_cast<uintptr_t>(p) % 16) == 0);
+}
+
+template <typename T>
+hipError_t contract_typed(const ContractArgs<T>& a, int nsplit, hipStream_t st) {
+  constexpr int TM = 1;
+  const int row_blocks = (a.rows + 64 * TM - 1) / (64 * TM);
+  dim3 grid(row_blocks, nsplit);
+  const int nt = (a.ncol + 15) / 16;
+  const bool vec = vec_ok(a.A, a.lda) && vec_ok(a.A2, a.lda2) && vec_ok(a.B, a.ldb);
+  if (vec) return contract_dispatch_nt<T, TM, true>(nt, grid, st, a);
+  return contract_dispatch_nt<T, TM, false>(nt, grid, st, a);
+}
+
 }  // namespace
 
-// Shared by the Jacobian launcher in dense.hip.
-hipError_t launch_jac_contract(int dtype, int m, int n, int rows, int K, const void* R,
-                               int64_t ldr, const void* r0, const void* W, int64_t ldw,
-                               int nsplit, int split_len, void* part, int npad, hipStream_t st) {
-  constexpr int TM = 1;
-  const int row_blocks = (rows + 64 * TM - 1) / (64 * TM);
-  dim3 grid(row_blocks, nsplit);
-  const int nt = npad / 16;
-  if (dtype == GNMPPI_F32) {
-    const float* Rf = static_cast<const float*>(R);
-    const float* Wf = static_cast<const float*>(W);
-    const bool vec = (ldr % 4 == 0) && (ldw % 4 == 0) &&
-                     (reinterpret_cast<uintptr_t>(Rf) % 16 == 0) &&
-                     (reinterpret_cast<uintptr_t>(Wf) % 16 == 0);
-    if (vec)
-      return contract_dispatch_nt<float, TM, true>(nt, grid, st, m, n, rows, K, Rf, ldr,
-                                                   static_cast<const float*>(r0), Wf, ldw,
-                                                   split_len, static_cast<float*>(part), npad);
-    return contract_dispatch_nt<float, TM, false>(nt, grid, st, m, n, rows, K, Rf, ldr,
-                                                  static_cast<const float*>(r0), Wf, ldw,
-                                                  split_len, static_cast<float*>(part), npad);
-  }
-  const double* Rd = static_cast<const double*>(R);
-  const double* Wd = static_cast<const double*>(W);
-  const bool vec = (ldr % 2 == 0) && (ldw % 2 == 0) &&
-                   (reinterpret_cast<uintptr_t>(Rd) % 16 == 0) &&
-                   (reinterpret_cast<uintptr_t>(Wd) % 16 == 0);
-  if (vec)
-    return contract_dispatch_nt<double, TM, true>(nt, grid, st, m, n, rows, K, Rd, ldr,
-                                                  static_cast<const double*>(r0), Wd, ldw,
-                                                  split_len, static_cast<double*>(part), npad);
-  return contract_dispatch_nt<double, TM, false>(nt, grid, st, m, n, rows, K, Rd, ldr,
-                                                 static_cast<const double*>(r0), Wd, ldw,
-                                                 split_len, static_cast<double*>(part), npad);
+hipError_t launch_contract(const ContractArgs<float>& a, int nsplit, hipStream_t st) {
+  return contract_typed(a, nsplit, st);
+}
+hipError_t launch_contract(const ContractArgs<double>& a, int nsplit, hipStream_t st) {
+  return contract_typed(a, nsplit, st);
 }
 
 }  // namespace gnm

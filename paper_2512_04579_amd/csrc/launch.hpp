@@ -27,7 +27,29 @@ hipError_t launch_mppi_update(int dtype, int n, int K, const void* C, const void
                               int64_t ldw, double temperature, void* U, void* weights,
                               int32_t* status, hipStream_t st);
 
-// Jacobian reconstruction; `work` holds the GEMM partials and G^{-1}.
+// out[y] = A B^T over k in [y split_len, (y+1) split_len) for y < nsplit.
+// Rows r < m come from A (minus asub[r] when asub is set), rows m <= r < rows
+// from A2; output columns are the ncol rows of B, written up to ocols.
+template <typename T>
+struct ContractArgs {
+  int m, rows, ncol, K;
+  const T* A;
+  int64_t lda;
+  const T* asub;
+  const T* A2;
+  int64_t lda2;
+  const T* B;
+  int64_t ldb;
+  int split_len;
+  T* out;
+  int64_t ldo;
+  int64_t split_stride;
+  int ocols;
+};
+hipError_t launch_contract(const ContractArgs<float>& a, int nsplit, hipStream_t st);
+hipError_t launch_contract(const ContractArgs<double>& a, int nsplit, hipStream_t st);
+
+// Jacobian reconstruction; `work` holds the GEMM partials, G, G^{-1} and S.
 struct JacPlan {
   int nsplit;        // k-splits of the S / G contraction
   int split_len;     // samples per split (a multiple of the MFMA k-step)
@@ -35,7 +57,9 @@ struct JacPlan {
   int npad;          // 16 * ncol_tiles
   int rows;          // m (+ n for LS)
   size_t part_bytes; // bytes of the partial sums
-  size_t ginv_off;   // byte offset of G^{-1} (n x n double) in work
+  size_t gsum_off;   // byte offset of G (n x n double, reduced) in work
+  size_t ginv_off;   // byte offset of G^{-1} (n x npad, working precision)
+  size_t s_off;      // byte offset of S (m x npad, working precision)
   size_t total;      // workspace bytes
 };
 JacPlan jacobian_plan(int dtype, int m, int n, int K, int method);
@@ -48,15 +72,14 @@ struct GgnPlan {
   int nsplit;        // row chunks of the J^T J contraction
   int chunk;         // rows per chunk
   int P;             // n + 1 (augmented with r0)
-  int tiles;         // 64-wide tiles covering P
-  size_t total;      // workspace bytes
+  int tiles;         // 16-wide MFMA tiles covering P
+  size_t part_bytes; // bytes of the per-chunk partial sums
+  size_t total;      // workspace bytes (partials + reduced matrix)
 };
 GgnPlan ggn_plan(int dtype, int m, int n);
 hipError_t launch_ggn(int dtype, int m, int n, const void* J, int64_t ldj, const void* r0,
                       int64_t inc_r0, double lm_lambda, void* dU, void* work,
                       int32_t* status, hipStream_t st);
 
-// Symmetric sweep (in-place Gauss-Jordan) of a packed SPD matrix in LDS.
-constexpr int kMaxSweepDim = 193;  // n <= 192 plus one augmented row
 
 }  // namespace gnm

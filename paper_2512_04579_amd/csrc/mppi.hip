@@ -25,7 +25,7 @@ __global__ void __launch_bounds__(kMppiThreads) mppi_update_kernel(
   const int tid = threadIdx.x;
 
   T cmin = infinity<T>();
-  for (int s = tid; s < K; s += blockDim.x) {
+  for (int s = tid; s < K; s += kMppiThreads) {
     const T c = C[s];
     if (finite(c) && c < cmin) cmin = c;
   }
@@ -35,7 +35,7 @@ __global__ void __launch_bounds__(kMppiThreads) mppi_update_kernel(
     return;
   }
   T z = 0;
-  for (int s = tid; s < K; s += blockDim.x) {
+  for (int s = tid; s < K; s += kMppiThreads) {
     const T c = C[s];
     const T ws = finite(c) ? exp(-(c - cmin) / temperature) : T(0);
     w[s] = ws;
@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(kMppiThreads) mppi_update_kernel(
   }
   if (blockIdx.x == 0) {
     if (weights)
-      for (int s = tid; s < K; s += blockDim.x) weights[s] = w[s] / z;
+      for (int s = tid; s < K; s += kMppiThreads) weights[s] = w[s] / z;
     if (tid == 0 && status) *status = GNMPPI_OK;
   }
 }

@@ -10,13 +10,21 @@
 // lane holding all 64 state entries, and the sequential horizon loop -- the
 // latency that bounds a single MPC instance -- shrinks accordingly.
 //
-// Residual rows are stored sample-fastest (row i of column s at i*ldr + s),
-// so the lanes of a wave that write the same row write consecutive columns.
+// Residual rows are stored sample-fastest (row i of column s at i*ldr + s).
+// The chain kernel stages each step's rows in LDS and writes every row of
+// the block as one contiguous segment; the double-integrator kernel's lanes
+// already write consecutive columns.
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace gnm {
 namespace {
+
+// Threads per block of the batch rollout kernels.  Loops stride by this
+// constant rather than blockDim.x: reading blockDim.x inside a loop costs a
+// load of the dispatch packet, and its wait would also drain every store the
+// rollout has in flight.
+constexpr int kBlock = 256;
 
 template <typename T>
 struct ChainDev {
@@ -24,27 +32,61 @@ struct ChainDev {
   T dt, k_lin, k_cub, inv_mass;
 };
 
-// Control of step-k entry idx for a perturbed sample (s >= 0) or the nominal.
+// Controls are read in two parts so that a rollout can prefetch the raw
+// loads several steps ahead and combine them only when the step runs:
+// load(idx) returns {a, b}, value(a, b) the control entry.
+//
+// Perturbed sample s >= 0 (or the nominal, s < 0): U[idx] + W[idx, s].  The
+// W load is unconditional (the nominal reads column 0 and masks it out), so
+// no lane waits on it inside a divergent branch.
 template <typename T>
 struct CtrlPerturbed {
   const T* __restrict__ U;
-  const T* __restrict__ W;
+  const T* __restrict__ W;  // may be null: every column uses U
   int64_t ldw;
   int s;
+  __device__ __forceinline__ void load(int idx, T& a, T& b) const {
+    a = U[idx];
+    b = W ? W[idx * ldw + (s >= 0 ? s : 0)] : T(0);
+  }
+  __device__ __forceinline__ T value(T a, T b) const { return s >= 0 ? a + b : a; }
   __device__ __forceinline__ T operator()(int idx) const {
-    T u = U[idx];
-    if (s >= 0) u += W[idx * ldw + s];
-    return u;
+    T a, b;
+    load(idx, a, b);
+    return value(a, b);
   }
 };
 
-// Control of a line-search candidate U + alpha dU.
+// Line-search candidate U + alpha dU.
 template <typename T>
 struct CtrlLine {
   const T* U;  // updated in place by the same kernel after a barrier
   const T* __restrict__ dU;
   T alpha;
+  __device__ __forceinline__ void load(int idx, T& a, T& b) const {
+    a = U[idx];
+    b = dU[idx];
+  }
+  __device__ __forceinline__ T value(T a, T b) const { return a + alpha * b; }
   __device__ __forceinline__ T operator()(int idx) const { return U[idx] + alpha * dU[idx]; }
+};
+
+// Controls staged in LDS: ctl[idx * stride + slot].  The batch rollout
+// stages U + W[:, s] for the block's samples (slot = sample in block), the
+// line search stages U and dU once (stride 1) and combines them per step.
+template <typename T>
+struct CtrlStaged {
+  const T* ctl;
+  int stride, slot;
+  __device__ __forceinline__ T operator()(int idx) const { return ctl[idx * stride + slot]; }
+};
+
+template <typename T>
+struct CtrlLineStaged {
+  const T* Us;
+  const T* dUs;
+  T alpha;
+  __device__ __forceinline__ T operator()(int idx) const { return Us[idx] + alpha * dUs[idx]; }
 };
 
 // ---- chain ---------------------------------------------------------------
@@ -76,15 +118,61 @@ __device__ __forceinline__ void chain_rhs(T px, T py, T vx, T vy, T u0, T u1,
   dvy = free_mass ? (ny - ty) * cd.inv_mass : T(0);
 }
 
+// Residual sinks of the chain rollout.  NoSink keeps only the cost.
+struct NoSink {
+  template <typename T>
+  __device__ __forceinline__ void step(int, int, bool, bool, T, T, T, T, T, T) {}
+};
+
+// StagedSink collects one step of residual rows of the block's samples in an
+// LDS tile (rows x samples, double-buffered) and then stores every row as one
+// contiguous segment of the sample-fastest R (or into r0 for the nominal
+// column).  One barrier per step; all threads of the block must call it.
+template <typename T, int G>
+struct StagedSink {
+  static constexpr int kSpb = kBlock / G;        // samples per block
+  static constexpr int kRows = 4 * G + 2;        // >= rows per step (4 M + 2)
+  T (*tile)[kRows][kSpb];                        // [2][kRows][kSpb] in LDS
+  T* R;
+  int64_t ldr;
+  T* r0;
+  int K, col0, M, grp;
+  __device__ __forceinline__ void step(int k, int i, bool has_mass, bool first, T e0, T e1, T e2,
+                                       T e3, T f0, T f1) {
+    T (*t)[kSpb] = tile[k & 1];
+    if (has_mass) {
+      t[2 * i][grp] = e0;
+      t[2 * i + 1][grp] = e1;
+      t[2 * M + 2 * i][grp] = e2;
+      t[2 * M + 2 * i + 1][grp] = e3;
+    }
+    if (first) {
+      t[4 * M][grp] = f0;
+      t[4 * M + 1][grp] = f1;
+    }
+    __syncthreads();
+    const int rows = 4 * M + 2;
+    const int64_t base = static_cast<int64_t>(k) * rows;
+    for (int idx = threadIdx.x; idx < rows * kSpb; idx += kBlock) {
+      const int row = idx / kSpb, s = idx % kSpb;
+      const int c = col0 + s;
+      if (c < K) {
+        if (R) R[(base + row) * ldr + c] = t[row][s];
+      } else if (c == K && r0) {
+        r0[base + row] = t[row][s];
+      }
+    }
+  }
+};
+
 // Rolls out one sample on the G lanes of its group and returns the group's
 // cost 1/2 ||r||^2 (identical in every lane of the group).  All lanes of the
 // wave must call this together (the DPP shifts read neighbouring lanes).
-template <typename T, int G, bool STORE, class Ctrl>
+template <typename T, int G, class Ctrl, class Sink>
 __device__ __forceinline__ T chain_rollout(const ChainDev<T>& cd, int N,
                                            const T* __restrict__ x0, const T* __restrict__ q,
                                            const T* __restrict__ r, const T* __restrict__ xref,
-                                           const Ctrl& ctrl, T* __restrict__ R, int64_t ldr,
-                                           int col, bool store_ok) {
+                                           const Ctrl& ctrl, Sink& sink) {
   const int i = threadIdx.x & (G - 1);
   const int M = cd.M;
   const bool has_mass = i < M;
@@ -100,50 +188,40 @@ __device__ __forceinline__ T chain_rollout(const ChainDev<T>& cd, int N,
   const T rpx = xref[2 * ii], rpy = xref[2 * ii + 1];
   const T rvx = xref[2 * M + 2 * ii], rvy = xref[2 * M + 2 * ii + 1];
   const T wu0 = dsqrt(T(2) * r[0]), wu1 = dsqrt(T(2) * r[1]);
-  const int64_t rows_per_step = 4 * M + 2;
   const T h = cd.dt, hh = T(0.5) * cd.dt, h6 = cd.dt / T(6);
   T cost = 0;
-  for (int k = 0; k < N; ++k) {
-    const T u0 = ctrl(2 * k), u1 = ctrl(2 * k + 1);
-    T a_px, a_py, a_vx, a_vy, b_px, b_py, b_vx, b_vy;
-    chain_rhs<T, G>(px, py, vx, vy, u0, u1, cd, first, free_mass, a_px, a_py, a_vx, a_vy);
-    T s_px = a_px, s_py = a_py, s_vx = a_vx, s_vy = a_vy;  // running k1 + 2 k2 + 2 k3 + k4
-    chain_rhs<T, G>(px + hh * a_px, py + hh * a_py, vx + hh * a_vx, vy + hh * a_vy, u0, u1, cd,
-                    first, free_mass, b_px, b_py, b_vx, b_vy);
-    s_px += T(2) * b_px; s_py += T(2) * b_py; s_vx += T(2) * b_vx; s_vy += T(2) * b_vy;
-    chain_rhs<T, G>(px + hh * b_px, py + hh * b_py, vx + hh * b_vx, vy + hh * b_vy, u0, u1, cd,
-                    first, free_mass, a_px, a_py, a_vx, a_vy);
-    s_px += T(2) * a_px; s_py += T(2) * a_py; s_vx += T(2) * a_vx; s_vy += T(2) * a_vy;
-    chain_rhs<T, G>(px + h * a_px, py + h * a_py, vx + h * a_vx, vy + h * a_vy, u0, u1, cd,
-                    first, free_mass, b_px, b_py, b_vx, b_vy);
-    s_px += b_px; s_py += b_py; s_vx += b_vx; s_vy += b_vy;
-    px += h6 * s_px;
-    py += h6 * s_py;
-    vx += h6 * s_vx;
-    vy += h6 * s_vy;
-    if (!free_mass) {  // the end mass moves with the commanded velocity
-      vx = u0;
-      vy = u1;
-    }
-    const T e0 = wpx * (px - rpx), e1 = wpy * (py - rpy);
-    const T e2 = wvx * (vx - rvx), e3 = wvy * (vy - rvy);
-    const T f0 = wu0 * u0, f1 = wu1 * u1;
-    if (has_mass) cost += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
-    if (first) cost += f0 * f0 + f1 * f1;
-    if constexpr (STORE) {
-      if (store_ok) {
-        const int64_t base = k * rows_per_step;
-        if (has_mass) {
-          R[(base + 2 * i) * ldr + col] = e0;
-          R[(base + 2 * i + 1) * ldr + col] = e1;
-          R[(base + 2 * M + 2 * i) * ldr + col] = e2;
-          R[(base + 2 * M + 2 * i + 1) * ldr + col] = e3;
-        }
-        if (first) {
-          R[(base + 4 * M) * ldr + col] = f0;
-          R[(base + 4 * M + 1) * ldr + col] = f1;
-        }
+  for (int k0 = 0; k0 < N; k0 += 4) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int k = k0 + t;
+      if (k >= N) break;  // uniform: every lane has the same horizon
+      const T u0 = ctrl(2 * k), u1 = ctrl(2 * k + 1);
+      T a_px, a_py, a_vx, a_vy, b_px, b_py, b_vx, b_vy;
+      chain_rhs<T, G>(px, py, vx, vy, u0, u1, cd, first, free_mass, a_px, a_py, a_vx, a_vy);
+      T s_px = a_px, s_py = a_py, s_vx = a_vx, s_vy = a_vy;  // running k1 + 2 k2 + 2 k3 + k4
+      chain_rhs<T, G>(px + hh * a_px, py + hh * a_py, vx + hh * a_vx, vy + hh * a_vy, u0, u1, cd,
+                      first, free_mass, b_px, b_py, b_vx, b_vy);
+      s_px += T(2) * b_px; s_py += T(2) * b_py; s_vx += T(2) * b_vx; s_vy += T(2) * b_vy;
+      chain_rhs<T, G>(px + hh * b_px, py + hh * b_py, vx + hh * b_vx, vy + hh * b_vy, u0, u1, cd,
+                      first, free_mass, a_px, a_py, a_vx, a_vy);
+      s_px += T(2) * a_px; s_py += T(2) * a_py; s_vx += T(2) * a_vx; s_vy += T(2) * a_vy;
+      chain_rhs<T, G>(px + h * a_px, py + h * a_py, vx + h * a_vx, vy + h * a_vy, u0, u1, cd,
+                      first, free_mass, b_px, b_py, b_vx, b_vy);
+      s_px += b_px; s_py += b_py; s_vx += b_vx; s_vy += b_vy;
+      px += h6 * s_px;
+      py += h6 * s_py;
+      vx += h6 * s_vx;
+      vy += h6 * s_vy;
+      if (!free_mass) {  // the end mass moves with the commanded velocity
+        vx = u0;
+        vy = u1;
       }
+      const T e0 = wpx * (px - rpx), e1 = wpy * (py - rpy);
+      const T e2 = wvx * (vx - rvx), e3 = wvy * (vy - rvy);
+      const T f0 = wu0 * u0, f1 = wu1 * u1;
+      if (has_mass) cost += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
+      if (first) cost += f0 * f0 + f1 * f1;
+      sink.step(k, i, has_mass, first, e0, e1, e2, e3, f0, f1);
     }
   }
 #pragma unroll
@@ -151,27 +229,72 @@ __device__ __forceinline__ T chain_rollout(const ChainDev<T>& cd, int N,
   return T(0.5) * cost;
 }
 
+// Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8).  Logical block g = (b % 8) * (gridDim.x / 8) + b / 8 gives each XCD
+// a contiguous range of samples, so the neighbouring 64-byte row segments of
+// adjacent blocks meet in the same L2 before they are written back.
+__device__ __forceinline__ int xcd_logical_block() {
+  const int per = gridDim.x >> 3;
+  return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
 template <typename T, int G>
 __global__ void __launch_bounds__(256) rollout_chain_kernel(
     ChainDev<T> cd, int N, const T* __restrict__ x0, const T* __restrict__ q,
     const T* __restrict__ r, const T* __restrict__ xref, const T* __restrict__ U,
     const T* __restrict__ W, int64_t ldw, int K, T* __restrict__ R, int64_t ldr,
-    T* __restrict__ C, T* __restrict__ r0, T* __restrict__ c0) {
+    T* __restrict__ C, T* __restrict__ r0, T* __restrict__ c0, int nblocks, int stage_ctl) {
+  constexpr int kSpb = kBlock / G;
+  extern __shared__ unsigned char ctl_raw[];
+  const int g = xcd_logical_block();
+  if (g >= nblocks) return;  // whole padding block: no barrier is shared with it
   const int ncol = K + (c0 ? 1 : 0);
-  const int gcol = (blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int grp = threadIdx.x / G;
+  const int gcol = g * kSpb + grp;
   const bool valid = gcol < ncol;
   const int col = valid ? gcol : ncol - 1;  // idle groups repeat a valid column, never store
   const bool nominal = col == K;
+  const int n = 2 * N;
+  if (stage_ctl) {
+    // the block's controls U + W[:, s] in one coalesced burst: ctl[idx][sample]
+    T* ctl = reinterpret_cast<T*>(ctl_raw);
+    const int col0 = g * kSpb;
+    for (int e = threadIdx.x; e < n * kSpb; e += kBlock) {
+      const int idx = e / kSpb, sl = e % kSpb;
+      const int c = col0 + sl;
+      T u = U[idx];
+      if (W != nullptr && c < K) u += W[idx * ldw + c];
+      ctl[e] = u;
+    }
+    __syncthreads();
+    CtrlStaged<T> ctrl{ctl, kSpb, grp};
+    T c;
+    if (R != nullptr || r0 != nullptr) {
+      __shared__ T tile[2][StagedSink<T, G>::kRows][kSpb];
+      StagedSink<T, G> sink{tile, R, ldr, r0, K, col0, cd.M, grp};
+      c = chain_rollout<T, G>(cd, N, x0, q, r, xref, ctrl, sink);
+    } else {
+      NoSink sink;
+      c = chain_rollout<T, G>(cd, N, x0, q, r, xref, ctrl, sink);
+    }
+    if (valid && (threadIdx.x & (G - 1)) == 0) {
+      if (nominal)
+        c0[0] = c;
+      else
+        C[col] = c;
+    }
+    return;
+  }
   CtrlPerturbed<T> ctrl{U, W, ldw, (nominal || W == nullptr) ? -1 : col};
-  T* out = nominal ? r0 : R;
-  const int64_t ld = nominal ? 1 : ldr;
-  const int ocol = nominal ? 0 : col;
   T c;
-  if (R != nullptr || r0 != nullptr)
-    c = chain_rollout<T, G, true>(cd, N, x0, q, r, xref, ctrl, out, ld, ocol,
-                                  valid && out != nullptr);
-  else
-    c = chain_rollout<T, G, false>(cd, N, x0, q, r, xref, ctrl, nullptr, 0, 0, false);
+  if (R != nullptr || r0 != nullptr) {
+    __shared__ T tile[2][StagedSink<T, G>::kRows][kSpb];
+    StagedSink<T, G> sink{tile, R, ldr, r0, K, g * kSpb, cd.M, grp};
+    c = chain_rollout<T, G>(cd, N, x0, q, r, xref, ctrl, sink);
+  } else {
+    NoSink sink;
+    c = chain_rollout<T, G>(cd, N, x0, q, r, xref, ctrl, sink);
+  }
   if (valid && (threadIdx.x & (G - 1)) == 0) {
     if (nominal)
       c0[0] = c;
@@ -230,7 +353,7 @@ __global__ void __launch_bounds__(256) rollout_di_kernel(
     int K, T* __restrict__ R, int64_t ldr, T* __restrict__ C, T* __restrict__ r0,
     T* __restrict__ c0) {
   const int ncol = K + (c0 ? 1 : 0);
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  const int col = blockIdx.x * kBlock + threadIdx.x;
   if (col >= ncol) return;  // no cross-lane traffic here, so idle lanes may leave
   const bool nominal = col == K;
   CtrlPerturbed<T> ctrl{U, W, ldw, (nominal || W == nullptr) ? -1 : col};
@@ -288,15 +411,32 @@ template <typename T, int G>
 __global__ void __launch_bounds__(1024) line_search_chain_kernel(
     ChainDev<T> cd, int N, const T* __restrict__ x0, const T* __restrict__ q,
     const T* __restrict__ r, const T* __restrict__ xref, T* U, const T* __restrict__ dU,
-    const T* __restrict__ alpha, int L, T* __restrict__ Cout, double* info) {
+    const T* __restrict__ alpha, int L, T* __restrict__ Cout, double* info, int stage_ctl) {
   __shared__ T costs[64];
   __shared__ int jstar;
+  extern __shared__ unsigned char ctl_raw[];
   const int j = threadIdx.x / G;
   const int jj = j < L ? j : L - 1;
-  CtrlLine<T> ctrl{U, dU, alpha[jj]};
-  const T c = chain_rollout<T, G, false>(cd, N, x0, q, r, xref, ctrl, nullptr, 0, 0, false);
+  const int n = 2 * N;
+  T c;
+  if (stage_ctl) {
+    T* Us = reinterpret_cast<T*>(ctl_raw);
+    T* dUs = Us + n;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+      Us[e] = U[e];
+      dUs[e] = dU[e];
+    }
+    __syncthreads();
+    CtrlLineStaged<T> ctrl{Us, dUs, alpha[jj]};
+    NoSink sink;
+    c = chain_rollout<T, G>(cd, N, x0, q, r, xref, ctrl, sink);
+  } else {
+    CtrlLine<T> ctrl{U, dU, alpha[jj]};
+    NoSink sink;
+    c = chain_rollout<T, G>(cd, N, x0, q, r, xref, ctrl, sink);
+  }
   if (j < L && (threadIdx.x & (G - 1)) == 0) costs[j] = c;
-  line_select_and_apply(costs, L, N * 2, U, dU, alpha, Cout, info, &jstar);
+  line_select_and_apply(costs, L, n, U, dU, alpha, Cout, info, &jstar);
 }
 
 template <typename T, int D>
@@ -315,6 +455,10 @@ __global__ void __launch_bounds__(64) line_search_di_kernel(
 }
 
 // ---- dispatch ---------------------------------------------------------------
+
+// Controls staged in LDS up to this size (the rest of the 160 KB holds the
+// residual tile); larger horizons read them from global memory.
+constexpr size_t kMaxStagedCtlBytes = 64 * 1024;
 
 inline int chain_group(int M) {
   int g = 1;
@@ -339,12 +483,15 @@ hipError_t rollout_typed(const gnmppi_problem& p, const T* x0, const T* U, const
   if (p.model == GNMPPI_MODEL_CHAIN) {
     const ChainDev<T> cd = chain_dev<T>(p);
     const int G = chain_group(p.n_masses);
-    const int threads = ncol * G;
-    dim3 grid((threads + 255) / 256);
+    const int nblocks = (ncol * G + 255) / 256;
+    dim3 grid((nblocks + 7) / 8 * 8);  // a multiple of the 8 XCDs, see xcd_logical_block()
+    const size_t ctl_bytes = static_cast<size_t>(p.N) * 2 * (256 / G) * sizeof(T);
+    const int stage = ctl_bytes <= kMaxStagedCtlBytes;
+    const size_t lds = stage ? ctl_bytes : 0;
 #define GNM_CHAIN_CASE(GG)                                                                      \
   case GG:                                                                                      \
-    hipLaunchKernelGGL((rollout_chain_kernel<T, GG>), grid, dim3(256), 0, st, cd, p.N, x0, q,   \
-                       r, xr, U, W, ldw, K, R, ldr, C, r0, c0);                                 \
+    hipLaunchKernelGGL((rollout_chain_kernel<T, GG>), grid, dim3(256), lds, st, cd, p.N, x0, q, \
+                       r, xr, U, W, ldw, K, R, ldr, C, r0, c0, nblocks, stage);                 \
     break;
     switch (G) {
       GNM_CHAIN_CASE(1)
@@ -387,10 +534,13 @@ hipError_t line_search_typed(const gnmppi_problem& p, const T* x0, T* U, const T
     const ChainDev<T> cd = chain_dev<T>(p);
     const int G = chain_group(p.n_masses);
     const int threads = ((L * G + 63) / 64) * 64;
+    const size_t ctl_bytes = static_cast<size_t>(p.N) * 2 * 2 * sizeof(T);
+    const int stage = ctl_bytes <= kMaxStagedCtlBytes;
+    const size_t lds = stage ? ctl_bytes : 0;
 #define GNM_LS_CASE(GG)                                                                          \
   case GG:                                                                                       \
-    hipLaunchKernelGGL((line_search_chain_kernel<T, GG>), dim3(1), dim3(threads), 0, st, cd, p.N, \
-                       x0, q, r, xr, U, dU, alpha, L, C, info);                                  \
+    hipLaunchKernelGGL((line_search_chain_kernel<T, GG>), dim3(1), dim3(threads), lds, st, cd,    \
+                       p.N, x0, q, r, xr, U, dU, alpha, L, C, info, stage);                      \
     break;
     switch (G) {
       GNM_LS_CASE(1)

@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(256) sample_kernel(int n, int Kdraw, T sigma, 
                                                      uint32_t k1, uint32_t s0, uint32_t s1,
                                                      int antithetic, T* __restrict__ W,
                                                      int64_t ldw) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.x * 256 + threadIdx.x;
   const int b = blockIdx.y;
   if (s >= Kdraw) return;
   const Philox4x32 x = philox4x32_10(Philox4x32{static_cast<uint32_t>(s), static_cast<uint32_t>(b), s0, s1}, k0, k1);
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(256) sample_kernel(int n, int Kdraw, T sigma, 
 template <typename T>
 __global__ void __launch_bounds__(256) sigma_points_kernel(int n, T scale, T* __restrict__ W,
                                                            int64_t ldw) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.x * 256 + threadIdx.x;
   const int row = blockIdx.y;
   if (s >= 2 * n) return;
   T v = 0;
