@@ -76,6 +76,12 @@ extern "C" {
  * MC: J = (dR W^T) / (K sigma2), the Monte-Carlo mean of Eq. (10) itself. */
 #define GNMPPI_JAC_LS 0
 #define GNMPPI_JAC_MC 1
+/* Flag for GNMPPI_JAC_LS: G^{-1} is already in `work`, computed from the same
+ * W by gnmppi_perturbation_gram (possibly on another stream, ordered before
+ * this call by the caller), so only S and J = S G^{-1} are formed; the rank
+ * check is then reported in gnmppi_perturbation_gram's status word and this
+ * call writes GNMPPI_OK to its own. */
+#define GNMPPI_JAC_GRAM_READY 0x100
 
 /* Problem data (Sec. 2).  Vectors are device arrays of the problem's dtype. */
 typedef struct gnmppi_problem {
@@ -162,6 +168,17 @@ int gnmppi_reconstruct_jacobian(int32_t dtype, int32_t m, int32_t n, int32_t K,
                                 double sigma2, void *J, int64_t ldj,
                                 void *work, size_t work_bytes,
                                 int32_t *status, void *stream);
+
+/* The W-only half of the LS reconstruction: G = W W^T and its inverse (the
+ * second-moment matrix that replaces Sigma in Eq. (10)), written into `work`
+ * (the Jacobian workspace, same size rule) for a later
+ * gnmppi_reconstruct_jacobian(..., GNMPPI_JAC_LS | GNMPPI_JAC_GRAM_READY, ...)
+ * with the same dtype, n, K, W and work.  Because it does not depend on the
+ * rollout, it can run concurrently with gnmppi_rollout on a second stream.
+ * A pivot below n 2^-52 max diag(G) sets *status = GNMPPI_ERANK. */
+int gnmppi_perturbation_gram(int32_t dtype, int32_t m, int32_t n, int32_t K, const void *W,
+                             int64_t ldw, void *work, size_t work_bytes, int32_t *status,
+                             void *stream);
 
 /* ---- a5: Generalized Gauss-Newton step (Eq. (13), Sec. 4.2) -------------
  * dU = -(J^T J + lm_lambda I)^{-1} J^T r0 for Phi = 1/2 ||.||^2, i.e. the

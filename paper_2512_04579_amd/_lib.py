@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libgnmppi.so")
 F32, F64 = 0, 1
 MODEL_DOUBLE_INTEGRATOR, MODEL_CHAIN = 1, 2
 JAC_LS, JAC_MC = 0, 1
+JAC_GRAM_READY = 0x100
 OK, EINVAL, EHIP, ENOTPD, ERANK, ENONFINITE, ENOSPACE = 0, -1, -2, -3, -4, -5, -6
 
 
@@ -54,6 +55,8 @@ SIGNATURES = {
                                               c_int64, c_void_p, c_void_p, c_int64, c_int32,
                                               c_double, c_void_p, c_int64, c_void_p, c_size_t,
                                               c_void_p, c_void_p]),
+    "gnmppi_perturbation_gram": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p, c_int64,
+                                           c_void_p, c_size_t, c_void_p, c_void_p]),
     "gnmppi_ggn_workspace": (c_size_t, [c_int32, c_int32, c_int32]),
     "gnmppi_ggn_step": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_int64, c_void_p, c_int64,
                                   c_double, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
@@ -172,6 +175,14 @@ def gnmppi_reconstruct_jacobian(R, r0, W, J, work, method: int = JAC_LS, sigma2:
         _dtype_code(J), m, n, K, _ptr(R), _ld(R), _ptr(r0), _ptr(W), _ld(W), int(method),
         float(sigma2), _ptr(J), _ld(J), _ptr(work), work.numel() * work.element_size(),
         _ptr(status), _stream(stream)))
+
+
+def gnmppi_perturbation_gram(W, work, m: int, status=None, K: int | None = None, stream=None):
+    n = W.shape[0]
+    K = W.shape[1] if K is None else K
+    _check("gnmppi_perturbation_gram", load().gnmppi_perturbation_gram(
+        _dtype_code(W), int(m), n, K, _ptr(W), _ld(W), _ptr(work),
+        work.numel() * work.element_size(), _ptr(status), _stream(stream)))
 
 
 def gnmppi_ggn_workspace(dtype: int, m: int, n: int) -> int:

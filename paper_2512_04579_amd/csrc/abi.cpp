@@ -103,13 +103,25 @@ int gnmppi_reconstruct_jacobian(int32_t dtype, int32_t m, int32_t n, int32_t K, 
   if (R == nullptr || r0 == nullptr || W == nullptr || J == nullptr || work == nullptr)
     return GNMPPI_EINVAL;
   if (ldr < K || ldw < K || ldj < n) return GNMPPI_EINVAL;
-  if (method != GNMPPI_JAC_LS && method != GNMPPI_JAC_MC) return GNMPPI_EINVAL;
-  if (method == GNMPPI_JAC_MC && (!(sigma2 > 0.0) || !std::isfinite(sigma2))) return GNMPPI_EINVAL;
+  const int32_t base = method & 0xff, flags = method & ~0xff;
+  if (base != GNMPPI_JAC_LS && base != GNMPPI_JAC_MC) return GNMPPI_EINVAL;
+  if (flags & ~GNMPPI_JAC_GRAM_READY) return GNMPPI_EINVAL;
+  if ((flags & GNMPPI_JAC_GRAM_READY) && base != GNMPPI_JAC_LS) return GNMPPI_EINVAL;
+  if (base == GNMPPI_JAC_MC && (!(sigma2 > 0.0) || !std::isfinite(sigma2))) return GNMPPI_EINVAL;
   if (!aligned256(work)) return GNMPPI_EINVAL;
   if (work_bytes < gnm::jacobian_plan(dtype, m, n, K, method).total) return GNMPPI_ENOSPACE;
   if (static_cast<int64_t>(m + n) * 192 >= (int64_t{1} << 31)) return GNMPPI_EINVAL;
   return status_of(gnm::launch_jacobian(dtype, m, n, K, R, ldr, r0, W, ldw, method, sigma2, J, ldj,
                                         work, status, as_stream(stream)));
+}
+
+int gnmppi_perturbation_gram(int32_t dtype, int32_t m, int32_t n, int32_t K, const void* W,
+                             int64_t ldw, void* work, size_t work_bytes, int32_t* status,
+                             void* stream) {
+  if (!dtype_ok(dtype) || m < 1 || n < 1 || n > 192 || K < 1) return GNMPPI_EINVAL;
+  if (W == nullptr || work == nullptr || ldw < K || !aligned256(work)) return GNMPPI_EINVAL;
+  if (work_bytes < gnm::jacobian_plan(dtype, m, n, K, GNMPPI_JAC_LS).total) return GNMPPI_ENOSPACE;
+  return status_of(gnm::launch_gram(dtype, m, n, K, W, ldw, work, status, as_stream(stream)));
 }
 
 size_t gnmppi_ggn_workspace(int32_t dtype, int32_t m, int32_t n) {

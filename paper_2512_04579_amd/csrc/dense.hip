@@ -4,13 +4,14 @@
 //  * reduce_sym_kernel -- adds the k-split / row-chunk partial sums of a
 //      symmetric matrix (lower triangle) into a full symmetric double matrix,
 //      one block per row so that every partial load is in flight at once.
-//  * sweep_kernel<R> -- one workgroup of 16 x 16 threads sweeps an SPD
-//      matrix with the symmetric sweep operator (Gauss-Jordan elimination
-//      without pivoting; for an SPD matrix its pivots are the Cholesky pivots
+//  * sweep_kernel<TD, R> -- one workgroup of TD x TD = 16 x 16 threads sweeps an SPD matrix
+//      with the symmetric sweep operator (Gauss-Jordan elimination without
+//      pivoting; for an SPD matrix its pivots are the Cholesky pivots
 //      squared).  Thread (ty, tx) keeps the lower-triangle elements
-//      (ty + 16 r, tx + 16 c), c <= r < R, in registers; each pivot
-//      broadcasts one column through LDS (double-buffered, so a single
-//      barrier per pivot) and every thread updates its own elements.
+//      (ty + TD r, tx + TD c), c <= r < R, in registers; each pivot
+//      broadcasts one column through LDS (double-buffered, so one barrier --
+//      or, for a single wave, one LDS fence -- per pivot) and every thread
+//      updates its own elements.
 //      Sweeping pivots 0..n-1 of [[H, g], [g^T, c]] leaves -H^{-1} in the
 //      leading block and H^{-1} g in the last row: the same kernel yields
 //      G^{-1} for the LS Jacobian and the GGN direction -(H^{-1} g) with no
@@ -76,37 +77,51 @@ __device__ __forceinline__ double recip(double d) {
   return x;
 }
 
-// One pivot p = 16 PB + pm of the sweep, written as a single rank-1 update:
+// Orders the LDS column broadcast of one pivot: a block-wide barrier for a
+// multi-wave sweep, a wavefront fence for the single-wave variant (a wave
+// executes its LDS operations in order, so no s_barrier is needed).
+template <int TD>
+__device__ __forceinline__ void sweep_sync() {
+  if constexpr (TD * TD > kWave) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// One pivot p = TD PB + pm of the sweep, written as a single rank-1 update:
 // with c = column p, d = c_p and z = c - (d + 1) e_p (c with its pivot entry
 // replaced by -1), the swept matrix is A_{\p} - z z^T / d, where A_{\p} is A
-// with row and column p set to zero.  PB is a compile-time column block, so
-// every register index is static and only the PB row / column blocks need a
-// select.
-template <int R, int PB>
+// with row and column p set to zero.  The TD x TD threads own elements
+// (ty + TD r, tx + TD c), c <= r < R.  PB is a compile-time column block, so
+// every register index is static and only the PB row / column blocks select.
+template <int TD, int R, int PB>
 __device__ __forceinline__ bool sweep_pivot(double (&A)[R][R], double* __restrict__ cv, int P,
                                             int pm, int tx, int ty, double tol) {
-  const int p = 16 * PB + pm;
+  const int p = TD * PB + pm;
   const bool col_owner = tx == pm, row_owner = ty == pm;
-  // publish column p: rows >= 16 PB from column block PB, rows < 16 PB from row p
+  // publish column p: rows >= TD PB from column block PB, rows < TD PB from row p
   if (col_owner) {
 #pragma unroll
     for (int r = PB; r < R; ++r) {
-      const int i = ty + 16 * r;
+      const int i = ty + TD * r;
       if (i < P) cv[i] = A[r][PB];
     }
   }
   if (row_owner) {
 #pragma unroll
-    for (int c = 0; c < PB; ++c) cv[tx + 16 * c] = A[PB][c];
+    for (int c = 0; c < PB; ++c) cv[tx + TD * c] = A[PB][c];
   }
-  __syncthreads();
+  sweep_sync<TD>();
   const double d = cv[p];
   if (!(d > tol)) return false;  // the same pivot in every thread: uniform
   const double inv = recip(d);
   double zi[R], zj[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int i = ty + 16 * r, j = tx + 16 * r;
+    const int i = ty + TD * r, j = tx + TD * r;
     zi[r] = i < P ? cv[i] : 0.0;
     zj[r] = j < P ? cv[j] : 0.0;
   }
@@ -126,55 +141,60 @@ __device__ __forceinline__ bool sweep_pivot(double (&A)[R][R], double* __restric
   return true;
 }
 
-template <int R, int PB>
-__device__ __forceinline__ bool sweep_block(double (&A)[R][R], double (*colv)[16 * R], int P,
+template <int TD, int R, int PB>
+__device__ __forceinline__ bool sweep_block(double (&A)[R][R], double (*colv)[TD * R], int P,
                                             int npiv, int tx, int ty, double tol) {
   if constexpr (PB < R) {
-    const int pend = min(16, npiv - 16 * PB);
+    const int pend = min(TD, npiv - TD * PB);
     for (int pm = 0; pm < pend; ++pm)
-      if (!sweep_pivot<R, PB>(A, colv[(16 * PB + pm) & 1], P, pm, tx, ty, tol)) return false;
-    if (16 * (PB + 1) < npiv) return sweep_block<R, PB + 1>(A, colv, P, npiv, tx, ty, tol);
+      if (!sweep_pivot<TD, R, PB>(A, colv[(TD * PB + pm) & 1], P, pm, tx, ty, tol)) return false;
+    if (TD * (PB + 1) < npiv) return sweep_block<TD, R, PB + 1>(A, colv, P, npiv, tx, ty, tol);
   }
   return true;
 }
 
-template <int R, typename TO>
-__global__ void __launch_bounds__(256) sweep_kernel(const double* __restrict__ M, int P, int npiv,
-                                                    int mode, TO* __restrict__ inv_out,
-                                                    int64_t ldo, TO* __restrict__ dir_out,
-                                                    int32_t* status, int fail_code) {
-  __shared__ double colv[2][16 * R];
+template <int TD, int R, typename TO>
+__global__ void __launch_bounds__(TD * TD) sweep_kernel(const double* __restrict__ M, int P,
+                                                        int npiv, int mode,
+                                                        TO* __restrict__ inv_out, int64_t ldo,
+                                                        TO* __restrict__ dir_out, int32_t* status,
+                                                        int fail_code) {
+  constexpr int kWaves = (TD * TD + kWave - 1) / kWave;
+  __shared__ double colv[2][TD * R];
+  __shared__ double wmax[kWaves];
   __shared__ double tol_s;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int tx = threadIdx.x % TD, ty = threadIdx.x / TD;
   double A[R][R];  // only c <= r is used
 #pragma unroll
   for (int r = 0; r < R; ++r)
 #pragma unroll
     for (int c = 0; c <= r; ++c) {
-      const int i = ty + 16 * r, j = tx + 16 * c;
+      const int i = ty + TD * r, j = tx + TD * c;
       A[r][c] = (i < P && j < P) ? M[static_cast<int64_t>(i) * P + j] : 0.0;
     }
   // pivot threshold from the largest diagonal entry, reduced from registers
   double dmax = 0;
 #pragma unroll
   for (int r = 0; r < R; ++r)
-    if (tx == ty && ty + 16 * r < npiv) dmax = fmax(dmax, A[r][r]);
+    if (tx == ty && ty + TD * r < npiv) dmax = fmax(dmax, A[r][r]);
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off, kWave));
-  if ((threadIdx.x & 63) == 0) colv[0][threadIdx.x >> 6] = dmax;
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = dmax;
   __syncthreads();
-  if (threadIdx.x == 0)
-    tol_s = static_cast<double>(npiv) * 0x1.0p-52 *
-            fmax(fmax(colv[0][0], colv[0][1]), fmax(colv[0][2], colv[0][3]));
+  if (threadIdx.x == 0) {
+    double mx = wmax[0];
+    for (int w = 1; w < kWaves; ++w) mx = fmax(mx, wmax[w]);
+    tol_s = static_cast<double>(npiv) * 0x1.0p-52 * mx;
+  }
   __syncthreads();
-  const bool ok = sweep_block<R, 0>(A, colv, P, npiv, tx, ty, tol_s);
+  const bool ok = sweep_block<TD, R, 0>(A, colv, P, npiv, tx, ty, tol_s);
   if (mode == kSweepInverse) {
     if (ok)
 #pragma unroll
       for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int c = 0; c <= r; ++c) {
-          const int i = ty + 16 * r, j = tx + 16 * c;
+          const int i = ty + TD * r, j = tx + TD * c;
           if (i < npiv && j <= i) {
             inv_out[i * ldo + j] = static_cast<TO>(-A[r][c]);
             inv_out[j * ldo + i] = static_cast<TO>(-A[r][c]);
@@ -182,26 +202,29 @@ __global__ void __launch_bounds__(256) sweep_kernel(const double* __restrict__ M
         }
   } else {
     // the augmented row npiv holds H^{-1} g in columns j < npiv
-    const int rb = npiv >> 4, rm = npiv & 15;
+    const int rb = npiv / TD, rm = npiv % TD;
 #pragma unroll
     for (int r = 0; r < R; ++r)
       if (r == rb && ty == rm)
 #pragma unroll
         for (int c = 0; c <= r; ++c) {
-          const int j = tx + 16 * c;
+          const int j = tx + TD * c;
           if (j < npiv) dir_out[j] = ok ? static_cast<TO>(-A[r][c]) : TO(0);
         }
   }
   if (threadIdx.x == 0 && status) *status = ok ? GNMPPI_OK : fail_code;
 }
 
+// 16 x 16 threads (one wave per SIMD); R = ceil(P / 16) <= 13 for P <= 208.
+// Measured at P = 101: 8 x 8 lanes (one wave, no barrier) is issue-bound and
+// 2.5x slower, 32 x 32 threads 15% slower.
 template <typename TO>
 hipError_t launch_sweep(int P, int npiv, int mode, const double* M, TO* inv_out, int64_t ldo,
                         TO* dir_out, int32_t* status, int fail_code, hipStream_t st) {
   const int R = (P + 15) / 16;
 #define GNM_SWEEP_CASE(RR)                                                                      \
   case RR:                                                                                      \
-    hipLaunchKernelGGL((sweep_kernel<RR, TO>), dim3(1), dim3(256), 0, st, M, P, npiv, mode,     \
+    hipLaunchKernelGGL((sweep_kernel<16, RR, TO>), dim3(1), dim3(256), 0, st, M, P, npiv, mode, \
                        inv_out, ldo, dir_out, status, fail_code);                               \
     break;
   switch (R) {
@@ -223,7 +246,8 @@ template <typename T>
 __global__ void __launch_bounds__(256) reduce_rows_kernel(const T* __restrict__ part, int nsplit,
                                                           int64_t split_stride, int ldp, int m,
                                                           int n, double scale, T* __restrict__ out,
-                                                          int64_t ldo) {
+                                                          int64_t ldo, int32_t* status) {
+  if (status && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *status = GNMPPI_OK;
   const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int c = blockIdx.x * 64 + (threadIdx.x & 63);
   if (i >= m || c >= n) return;
@@ -315,9 +339,21 @@ hipError_t launch_gram(int nt, int nblocks, hipStream_t st, int m, int n, const 
   return hipGetLastError();
 }
 
-__global__ void set_status_kernel(int32_t* status, int32_t value) { *status = value; }
-
 }  // namespace
+
+// k-split plan: enough slices that ~1.5k waves (16 rows each) cover the
+// machine, at least two MFMA k-steps per slice.
+static void split_plan(int rows, int K, int step, int& nsplit_out, int& split_len_out) {
+  const int waves_per_split = (rows + 15) / 16;
+  const int ksteps = (K + step - 1) / step;
+  int nsplit = (1536 + waves_per_split - 1) / waves_per_split;
+  const int max_split = ksteps / 2 > 1 ? ksteps / 2 : 1;
+  if (nsplit > max_split) nsplit = max_split;
+  if (nsplit < 1) nsplit = 1;
+  const int steps_per_split = (ksteps + nsplit - 1) / nsplit;
+  nsplit_out = (ksteps + steps_per_split - 1) / steps_per_split;
+  split_len_out = steps_per_split * step;
+}
 
 JacPlan jacobian_plan(int dtype, int m, int n, int K, int method) {
   JacPlan p{};
@@ -325,22 +361,58 @@ JacPlan jacobian_plan(int dtype, int m, int n, int K, int method) {
   const int step = dtype == GNMPPI_F32 ? 32 : 16;
   p.ncol_tiles = (n + 15) / 16;
   p.npad = 16 * p.ncol_tiles;
-  p.rows = m + (method == GNMPPI_JAC_LS ? n : 0);
-  const int waves_per_split = (p.rows + 15) / 16;
-  const int ksteps = (K + step - 1) / step;
-  int nsplit = (1536 + waves_per_split - 1) / waves_per_split;
-  const int max_split = ksteps / 2 > 1 ? ksteps / 2 : 1;
-  if (nsplit > max_split) nsplit = max_split;
-  if (nsplit < 1) nsplit = 1;
-  const int steps_per_split = (ksteps + nsplit - 1) / nsplit;
-  p.nsplit = (ksteps + steps_per_split - 1) / steps_per_split;
-  p.split_len = steps_per_split * step;
-  p.part_bytes = align_up(static_cast<size_t>(p.nsplit) * p.rows * p.npad * esz);
+  const int base = method & 0xff;
+  const bool ready = (method & GNMPPI_JAC_GRAM_READY) != 0;
+  p.rows = m + ((base == GNMPPI_JAC_LS && !ready) ? n : 0);
+  split_plan(p.rows, K, step, p.nsplit, p.split_len);
+  // the partial-sum area is sized for the largest row set (m + n) so that
+  // every method shares one workspace layout
+  int ns_max, sl_max;
+  split_plan(m + n, K, step, ns_max, sl_max);
+  int ns_m, sl_m;
+  split_plan(m, K, step, ns_m, sl_m);
+  const size_t part_elems = static_cast<size_t>(ns_max > ns_m ? ns_max : ns_m) * (m + n) * p.npad;
+  p.part_bytes = align_up(part_elems * esz);
   p.gsum_off = p.part_bytes;
   p.ginv_off = p.gsum_off + align_up(static_cast<size_t>(n) * n * 8);
   p.s_off = p.ginv_off + align_up(static_cast<size_t>(n) * p.npad * esz);
-  p.total = p.s_off + align_up(static_cast<size_t>(m) * p.npad * esz);
+  split_plan(n, K, step, p.gsplit, p.gsplit_len);
+  p.gpart_off = p.s_off + align_up(static_cast<size_t>(m) * p.npad * esz);
+  p.total = p.gpart_off + align_up(static_cast<size_t>(p.gsplit) * n * p.npad * esz);
   return p;
+}
+
+// G = W W^T reduced to a full double matrix and inverted into Ginv (n x npad).
+template <typename T>
+hipError_t gram_inverse_typed(const JacPlan& pl, int n, int K, const T* W, int64_t ldw,
+                              char* wk, const T* part, int nsplit, int64_t split_stride, int row0,
+                              int32_t* status, hipStream_t st) {
+  double* Gsum = reinterpret_cast<double*>(wk + pl.gsum_off);
+  T* Ginv = reinterpret_cast<T*>(wk + pl.ginv_off);
+  hipLaunchKernelGGL(reduce_sym_kernel<T>, dim3(n), dim3(256), 0, st, part, nsplit, split_stride,
+                     row0, pl.npad, n, n, 0.0, Gsum);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  (void)K;
+  (void)W;
+  (void)ldw;
+  return launch_sweep<T>(n, n, kSweepInverse, Gsum, Ginv, pl.npad, nullptr, status, GNMPPI_ERANK,
+                         st);
+}
+
+template <typename T>
+hipError_t gram_typed(int m, int n, int K, const T* W, int64_t ldw, void* work, int32_t* status,
+                      hipStream_t st) {
+  const int dtype = sizeof(T) == 4 ? GNMPPI_F32 : GNMPPI_F64;
+  const JacPlan pl = jacobian_plan(dtype, m, n, K, GNMPPI_JAC_LS);
+  char* wk = static_cast<char*>(work);
+  T* gpart = reinterpret_cast<T*>(wk + pl.gpart_off);
+  const int64_t split_stride = static_cast<int64_t>(n) * pl.npad;
+  ContractArgs<T> c{n, n, n, K, W, ldw, nullptr, nullptr, 0, W, ldw, pl.gsplit_len,
+                    gpart, pl.npad, split_stride, pl.npad};
+  hipError_t e = launch_contract(c, pl.gsplit, st);
+  if (e != hipSuccess) return e;
+  return gram_inverse_typed<T>(pl, n, K, W, ldw, wk, gpart, pl.gsplit, split_stride, 0, status, st);
 }
 
 template <typename T>
@@ -349,44 +421,47 @@ hipError_t jacobian_typed(int m, int n, int K, const T* R, int64_t ldr, const T*
                           int32_t* status, hipStream_t st) {
   const int dtype = sizeof(T) == 4 ? GNMPPI_F32 : GNMPPI_F64;
   const JacPlan pl = jacobian_plan(dtype, m, n, K, method);
+  const int base = method & 0xff;
+  const bool ready = (method & GNMPPI_JAC_GRAM_READY) != 0;
   char* wk = static_cast<char*>(work);
   T* part = reinterpret_cast<T*>(wk);
   const int64_t split_stride = static_cast<int64_t>(pl.rows) * pl.npad;
-  // S = (R - r0 1^T) W^T and (LS) G = W W^T, as k-split partial sums
+  // S = (R - r0 1^T) W^T and (LS, unless ready) G = W W^T, as k-split partial sums
   ContractArgs<T> c1{m, pl.rows, n, K, R, ldr, r0, W, ldw, W, ldw, pl.split_len,
                      part, pl.npad, split_stride, pl.npad};
   hipError_t e = launch_contract(c1, pl.nsplit, st);
   if (e != hipSuccess) return e;
   const dim3 rgrid((n + 63) / 64, (m + 3) / 4);
-  if (method == GNMPPI_JAC_MC) {
+  if (base == GNMPPI_JAC_MC) {
+    // MC has no factorisation that can fail: the reduction reports success
     hipLaunchKernelGGL(reduce_rows_kernel<T>, rgrid, dim3(256), 0, st, part, pl.nsplit,
                        split_stride, pl.npad, m, n, 1.0 / (static_cast<double>(K) * sigma2), J,
-                       ldj);
-    e = hipGetLastError();
-    if (e == hipSuccess && status) {
-      // MC has no factorisation that can fail; report success in stream order.
-      hipLaunchKernelGGL(set_status_kernel, dim3(1), dim3(1), 0, st, status, GNMPPI_OK);
-      e = hipGetLastError();
-    }
-    return e;
+                       ldj, status);
+    return hipGetLastError();
   }
-  double* Gsum = reinterpret_cast<double*>(wk + pl.gsum_off);
   T* Ginv = reinterpret_cast<T*>(wk + pl.ginv_off);
   T* S = reinterpret_cast<T*>(wk + pl.s_off);
-  hipLaunchKernelGGL(reduce_sym_kernel<T>, dim3(n), dim3(256), 0, st, part, pl.nsplit,
-                     split_stride, m, pl.npad, n, n, 0.0, Gsum);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  e = launch_sweep<T>(n, n, kSweepInverse, Gsum, Ginv, pl.npad, nullptr, status, GNMPPI_ERANK, st);
-  if (e != hipSuccess) return e;
+  if (!ready) {
+    e = gram_inverse_typed<T>(pl, n, K, W, ldw, wk, part, pl.nsplit, split_stride, m, status, st);
+    if (e != hipSuccess) return e;
+  }
+  // with a ready G the rank check belongs to gnmppi_perturbation_gram's own
+  // status word and the S reduction reports success here
   hipLaunchKernelGGL(reduce_rows_kernel<T>, rgrid, dim3(256), 0, st, part, pl.nsplit, split_stride,
-                     pl.npad, m, n, 1.0, S, pl.npad);
+                     pl.npad, m, n, 1.0, S, pl.npad, ready ? status : nullptr);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   // J = S G^{-1} = S (G^{-1})^T: the same contraction over the decision index
   ContractArgs<T> c2{m, m, n, n, S, pl.npad, nullptr, nullptr, 0, Ginv, pl.npad, n,
                      J, ldj, 0, n};
   return launch_contract(c2, 1, st);
+}
+
+hipError_t launch_gram(int dtype, int m, int n, int K, const void* W, int64_t ldw, void* work,
+                       int32_t* status, hipStream_t st) {
+  if (dtype == GNMPPI_F32)
+    return gram_typed<float>(m, n, K, static_cast<const float*>(W), ldw, work, status, st);
+  return gram_typed<double>(m, n, K, static_cast<const double*>(W), ldw, work, status, st);
 }
 
 hipError_t launch_jacobian(int dtype, int m, int n, int K, const void* R, int64_t ldr,

@@ -60,9 +60,14 @@ struct JacPlan {
   size_t gsum_off;   // byte offset of G (n x n double, reduced) in work
   size_t ginv_off;   // byte offset of G^{-1} (n x npad, working precision)
   size_t s_off;      // byte offset of S (m x npad, working precision)
+  int gsplit;        // k-splits of the separate G = W W^T contraction
+  int gsplit_len;
+  size_t gpart_off;  // byte offset of its partial sums (gsplit x n x npad)
   size_t total;      // workspace bytes
 };
 JacPlan jacobian_plan(int dtype, int m, int n, int K, int method);
+hipError_t launch_gram(int dtype, int m, int n, int K, const void* W, int64_t ldw, void* work,
+                       int32_t* status, hipStream_t st);
 hipError_t launch_jacobian(int dtype, int m, int n, int K, const void* R, int64_t ldr,
                            const void* r0, const void* W, int64_t ldw, int method,
                            double sigma2, void* J, int64_t ldj, void* work,

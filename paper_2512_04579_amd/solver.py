@@ -70,8 +70,14 @@ class GNMPPI:
     Philox normals) or "sigma_points" (Method E, the 2n-point Dirac mixture)."""
 
     def __init__(self, dprob: DeviceProblem, x0, settings, seed: int = 1, U0=None,
-                 sampler: str = "gaussian", max_iters: int | None = None):
+                 sampler: str = "gaussian", max_iters: int | None = None, overlap: bool = False):
         self.p = dprob
+        # G = W W^T and its inverse depend only on W: with ``overlap`` they are
+        # factored on a side stream while the rollout runs (LS estimator only).
+        # Off by default: with eager launches the cross-stream waits cost more
+        # than the overlap saves at the c2 size.
+        self.overlap = overlap and settings.jacobian == "ls"
+        self.side = torch.cuda.Stream(device=dprob.device) if self.overlap else None
         self.s = settings
         self.seed = int(seed)
         self.sampler = sampler
@@ -94,7 +100,7 @@ class GNMPPI:
         self.C_line = torch.zeros(settings.n_alpha, dtype=dt, device=dev)
         iters = max_iters if max_iters is not None else settings.iters
         self.info = torch.zeros(max(iters, 1), 3, dtype=torch.float64, device=dev)
-        self.status = torch.zeros(iters if iters else 1, 2, dtype=torch.int32, device=dev)
+        self.status = torch.zeros(iters if iters else 1, 3, dtype=torch.int32, device=dev)
         code = _lib.F32 if dt == torch.float32 else _lib.F64
         self.work_j = _workspace(_lib.gnmppi_jacobian_workspace(code, m, n, K), dev)
         self.work_g = _workspace(_lib.gnmppi_ggn_workspace(code, m, n), dev)
@@ -117,11 +123,20 @@ class GNMPPI:
             _lib.gnmppi_sigma_points(W, sig)
         else:
             _lib.gnmppi_sample(W, sig, self.seed, it, antithetic=self.s.antithetic, K=K)
+        if self.overlap:
+            main = torch.cuda.current_stream()
+            self.side.wait_stream(main)
+            with torch.cuda.stream(self.side):
+                _lib.gnmppi_perturbation_gram(W, self.work_j, self.m, self.status[it, 2:3], K)
         tick.next("rollout")
         _lib.gnmppi_rollout(self.p, self.x0, self.U, W, K, self.R[:, :K], self.C, self.r0, self.c0)
         tick.next("jacobian")
+        method = self.method
+        if self.overlap:
+            torch.cuda.current_stream().wait_stream(self.side)
+            method |= _lib.JAC_GRAM_READY
         _lib.gnmppi_reconstruct_jacobian(self.R[:, :K], self.r0, W, self.J, self.work_j,
-                                         self.method, sig * sig, self.status[it, 0:1], K)
+                                         method, sig * sig, self.status[it, 0:1], K)
         tick.next("ggn_step")
         _lib.gnmppi_ggn_step(self.J, self.r0, self.s.lm_lambda, self.dU, self.work_g,
                              self.status[it, 1:2])

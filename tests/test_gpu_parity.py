@@ -7,6 +7,8 @@ N=50, K=4096, the launch configuration the benchmark times), the limits
 degenerate inputs (non-finite costs, rank-deficient perturbations, a
 singular normal matrix).
 """
+import json
+import os
 import zlib
 
 import numpy as np
@@ -236,6 +238,39 @@ def test_jacobian_mc_matches_oracle(case):
     assert_parity(J, jacobian.mc(R, W, sigma * sigma), dtype, "J (MC)")
 
 
+@pytest.mark.parametrize("case", ["c1", "c2", "chain_f32_ragged"])
+def test_jacobian_with_gram_factored_separately(case):
+    # gnmppi_perturbation_gram (W only) then GRAM_READY: same J as the oracle
+    prob, dtype, K, sigma, R, W = _jacobian_inputs(case)
+    m, n = R.shape[0], W.shape[0]
+    Rd, Wd, r0d = padded(R[:, 1:], dtype), padded(W, dtype), to_dev(R[:, 0], dtype)
+    J = to_dev(np.zeros((m, n)), dtype)
+    code = _lib.F32 if dtype == "f32" else _lib.F64
+    work = torch.empty(_lib.gnmppi_jacobian_workspace(code, m, n, K), dtype=torch.uint8, device=device())
+    st = torch.full((2,), 99, dtype=torch.int32, device=device())
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        _lib.gnmppi_perturbation_gram(Wd, work, m, st[1:2], K)
+    torch.cuda.current_stream().wait_stream(side)
+    _lib.gnmppi_reconstruct_jacobian(Rd, r0d, Wd, J, work, _lib.JAC_LS | _lib.JAC_GRAM_READY, 0.0,
+                                     st[0:1], K)
+    _sync()
+    assert host(st).tolist() == [0, 0]
+    assert_parity(host(J), jacobian.ls(R, W), dtype, "J (gram on a side stream)")
+
+
+def test_perturbation_gram_reports_rank_deficiency():
+    rng = np.random.default_rng(6)
+    n, K = 12, 10
+    Wd = padded(rng.standard_normal((n, K)), "f64")
+    work = torch.empty(_lib.gnmppi_jacobian_workspace(_lib.F64, 30, n, K), dtype=torch.uint8, device=device())
+    st = torch.full((1,), 99, dtype=torch.int32, device=device())
+    _lib.gnmppi_perturbation_gram(Wd, work, 30, st, K)
+    _sync()
+    assert int(st.item()) == _lib.ERANK
+
+
 def test_jacobian_unaligned_leading_dimensions_take_the_scalar_path():
     prob, dtype, K, sigma, R, W = _jacobian_inputs("chain_f64_ragged")
     J, st = _run_jacobian(R, W, dtype, ldw=K + 1, ldr=K + 3)
@@ -404,6 +439,20 @@ def test_c2_first_iteration_matches_oracle():
     assert_parity([costs[0]], [h.cost[0]], "f32", "cost after one iteration")
     assert_parity(host(solver.U), Uo, "f32", "U after one iteration", tol=1e-3)
     assert costs[0] < ocp.cost(rp, rnd(w.x0, "f32"), np.zeros(p.n))
+
+
+@pytest.mark.parametrize("overlap", [False, True])
+def test_c1_solver_with_and_without_stream_overlap(overlap):
+    w = wl.c1()
+    solver = GNMPPI(DeviceProblem(w.problem, "f64"), w.x0, w.settings, seed=3, max_iters=2,
+                    overlap=overlap)
+    solver.solve(2)
+    _sync()
+    costs, _, status = solver.history(2)
+    assert (status == 0).all()
+    with open(os.path.join(os.path.dirname(__file__), "golden", "reference_optima.json")) as f:
+        cstar = json.load(f)["c1"]["cstar"]
+    assert abs(costs[0] - cstar) / cstar < 1e-10
 
 
 def test_plain_mppi_decreases_the_cost_on_c1():
