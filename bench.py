@@ -59,6 +59,28 @@ def algorithmic_work(prob, K: int, L: int, esize: int):
     }
 
 
+def rollout_traffic(name: str, esize: int):
+    """HBM bytes per rollout launch from the committed rocprofv3 PMC summary
+    (FETCH_SIZE and WRITE_SIZE, copy-calibrated), or None when that summary
+    was taken for another workload or the kernel source has changed since."""
+    path = os.path.join(ROOT, "profiles", f"{name}_rollout_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_2512_04579_amd/csrc/rollout.hip", "paper_2512_04579_amd/csrc/common.hpp"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if kv.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(w, budget_s: float):
     """The oracle's GN-MPPI iteration timed on the host cores (FP64 NumPy)."""
     import numpy as np
@@ -88,13 +110,16 @@ def cpu_baseline(w, budget_s: float):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4"])
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-gap", action="store_true")
     ap.add_argument("--mppi-iters", type=int, default=1500)
+    ap.add_argument("--graph-chunk", type=int, default=50, help="iterations per captured graph")
+    ap.add_argument("--eager", action="store_true", help="time eager launches instead of graphs")
+    ap.add_argument("--kernel-reps", type=int, default=50, help="rollout launches for the roofline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
     args = ap.parse_args()
@@ -127,49 +152,79 @@ def main():
     p, st = w.problem, w.settings
     dp = DeviceProblem(p, w.dtype)
     esize = 4 if w.dtype == "f32" else 8
-    total = args.warmup + args.steps
-    solver = GNMPPI(dp, w.x0, st, seed=w.noise_seed, max_iters=total)
-    for it in range(args.warmup):
-        solver.step(it)
+    # The timed region replays HIP graphs of `chunk` captured iterations, so the
+    # host enqueues one launch per chunk instead of ~12 kernels per iteration.
+    chunk = min(args.steps, args.graph_chunk)
+    reps = max(1, args.steps // chunk)
+    steps = reps * chunk
+    solver = GNMPPI(dp, w.x0, st, seed=w.noise_seed, max_iters=chunk + 1)
+    graph = solver.capture(chunk) if not args.eager else None
+    for _ in range(max(1, args.warmup // chunk)):
+        graph.replay() if graph else [solver.step(it) for it in range(chunk)]
     torch.cuda.synchronize()
-    marks = {}
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     wall0 = time.perf_counter()
     t_start.record()
-    for it in range(args.warmup, total):
-        solver.step(it, marks)
+    for _ in range(reps):
+        if graph:
+            graph.replay()
+        else:
+            for it in range(chunk):
+                solver.step(it)
     t_end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms_total = t_start.elapsed_time(t_end)
-    ms_per_step = ms_total / args.steps
-    per_call_us = {k: 1e3 * float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in marks.items()}
-    _, _, status = solver.history(total)
+    ms_per_step = ms_total / steps
+    _, _, status = solver.history(chunk)
     assert (status == 0).all(), f"device status words: {np.unique(status)}"
+
+    # Per-call durations: HIP events around each library call of eager
+    # iterations.  A device-side spin before each iteration holds the stream
+    # until the host has enqueued the whole iteration, so the host's launch
+    # gaps stay out of the per-call times.  Then the rollout kernel alone in a
+    # back-to-back loop on the launch stream gives the roofline's duration.
+    marks = {}
+    for it in range(chunk):
+        torch.cuda._sleep(1_000_000)
+        solver.step(it, marks)
+        torch.cuda.synchronize()
+    per_call_us = {k: 1e3 * float(np.median([a.elapsed_time(b) for a, b in v])) for k, v in marks.items()}
+    Kc = solver.K
+    Wv, Rv = solver.W[:, :Kc], solver.R[:, :Kc]
+    for _ in range(3):
+        _lib.gnmppi_rollout(dp, solver.x0, solver.U, Wv, Kc, Rv, solver.C, solver.r0, solver.c0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.kernel_reps):
+        _lib.gnmppi_rollout(dp, solver.x0, solver.U, Wv, Kc, Rv, solver.C, solver.r0, solver.c0)
+    e1.record()
+    torch.cuda.synchronize()
+    rollout_us = e0.elapsed_time(e1) * 1e3 / args.kernel_reps
+    per_call_us["rollout_kernel"] = rollout_us
+    args.steps = steps
 
     K, L, N = solver.K, st.n_alpha, p.N
     work = algorithmic_work(p, K, L, esize)
-    dominant = max(per_call_us, key=per_call_us.get)
-    # roofline of the rollout kernel (one kernel per call) and of the dominant call
-    def roof(name):
-        t = per_call_us[name] * 1e-6
-        wk = work[name]
-        if name in ("jacobian",):
-            peak = PEAK["fp32_TFLOPs"] if esize == 4 else PEAK["fp64_TFLOPs"]
-            ach = wk["flops"] / t / 1e12
-            return {"kernel": name, "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                    "frac": ach / peak, "traffic": None}
-        if name in ("rollout", "sample"):
-            ach = wk["bytes"] / t / 1e9
-            return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": PEAK["hbm_GBps"],
-                    "unit": "GB/s", "frac": ach / PEAK["hbm_GBps"], "traffic": None,
-                    "alu_frac": wk["flops"] / t / 1e12 / PEAK["fp32_TFLOPs" if esize == 4 else "fp64_TFLOPs"]}
-        peak = PEAK["fp64_TFLOPs"]
-        ach = wk["flops"] / t / 1e12
-        return {"kernel": name, "bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": None}
+    fp_peak = PEAK["fp32_TFLOPs"] if esize == 4 else PEAK["fp64_TFLOPs"]
+    calls = {}
+    for name, us in per_call_us.items():
+        wk = work["rollout" if name == "rollout_kernel" else name]
+        t = us * 1e-6
+        entry = {"us": us, "GBps": wk["bytes"] / t / 1e9, "TFLOPs": wk["flops"] / t / 1e12}
+        entry["hbm_frac"] = entry["GBps"] / PEAK["hbm_GBps"]
+        entry["fp_frac"] = entry["TFLOPs"] / fp_peak
+        calls[name] = entry
+    # Roofline of the rollout kernel: the largest single launch of the
+    # iteration and the one library call that is exactly one kernel, so its
+    # HIP-event time on the launch stream is the kernel's duration.
+    ro = calls["rollout_kernel"]
+    roofline = {"kernel": "rollout_chain_kernel" if p.model == 2 else "rollout_di_kernel",
+                "bound": "hbm", "achieved": ro["GBps"], "peak": PEAK["hbm_GBps"], "unit": "GB/s",
+                "frac": ro["hbm_frac"], "traffic": rollout_traffic(w.name, esize),
+                "algorithmic_bytes": work["rollout"]["bytes"], "launch_us": ro["us"],
+                "alu_TFLOPs": ro["TFLOPs"], "alu_frac": ro["fp_frac"]}
 
     result = {
         "metric": METRIC,
@@ -188,10 +243,10 @@ def main():
                    "m": p.m, "n": p.n, "line_search_candidates": L, "jacobian": st.jacobian},
         "sample_steps_per_s": args.steps * (K + 1 + L) * N / (ms_total * 1e-3),
         "host_wall_s": wall,
-        "per_call_us": per_call_us,
-        "iteration_over_rollout": ms_per_step * 1e3 / per_call_us["rollout"],
-        "roofline": roof(dominant),
-        "roofline_rollout": roof("rollout"),
+        "per_call": calls,
+        "iteration_over_rollout": ms_per_step * 1e3 / per_call_us["rollout_kernel"],
+        "timed_with": "eager launches" if args.eager else f"HIP graph replays of {chunk} iterations",
+        "roofline": roofline,
     }
 
     if not args.no_time_to_gap:

@@ -145,6 +145,26 @@ class GNMPPI:
                                 self.info[it])
         tick.stop()
 
+    def capture(self, iters: int, it0: int = 0):
+        """Captures iterations it0 .. it0 + iters - 1 into one HIP graph.
+
+        Every call only enqueues kernels on the current stream and the
+        iteration-dependent arguments (sampling scale, Philox stream, output
+        rows) are fixed at capture, so ``graph.replay()`` re-runs exactly these
+        iterations from the current U with a single launch.  The graph owns no
+        memory of its own: all buffers belong to this solver."""
+        side = torch.cuda.Stream(device=self.p.device)
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):  # warm-up outside capture, as torch requires
+            self.step(it0)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            for it in range(it0, it0 + iters):
+                self.step(it)
+        return graph
+
     def solve(self, iters: int | None = None, events: bool = False):
         """Runs ``iters`` iterations; returns (costs, alphas, statuses, event list)."""
         iters = self.s.iters if iters is None else iters

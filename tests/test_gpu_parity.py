@@ -455,6 +455,29 @@ def test_c1_solver_with_and_without_stream_overlap(overlap):
     assert abs(costs[0] - cstar) / cstar < 1e-10
 
 
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_graph_replays_match_eager_iterations(name):
+    w = wl.get(name)
+    dp = DeviceProblem(w.problem, w.dtype)
+    eager = GNMPPI(dp, w.x0, w.settings, seed=5, max_iters=3)
+    for it in range(3):
+        eager.step(it)
+    _sync()
+    U_ref, info_ref = host(eager.U), host(eager.info)
+    g = GNMPPI(dp, w.x0, w.settings, seed=5, max_iters=3)
+    graph = g.capture(3)
+    for rep in range(3):
+        g.U.zero_()                      # fill kernel, outside the graph
+        g.info.zero_()
+        _lib.gnmppi_rollout(dp, g.x0, g.U, None, 0, None, None, None, g.c0)  # eager work between
+        _sync()
+        graph.replay()
+        _sync()
+        np.testing.assert_array_equal(host(g.U), U_ref, err_msg=f"replay {rep}")
+        np.testing.assert_array_equal(host(g.info), info_ref, err_msg=f"replay {rep}")
+        assert (g.history(3)[2] == 0).all()
+
+
 def test_plain_mppi_decreases_the_cost_on_c1():
     w = wl.c1()
     solver = PlainMPPI(DeviceProblem(w.problem, "f64"), w.x0, w.settings, max_iters=30)
