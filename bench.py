@@ -240,7 +240,8 @@ def main():
         "dtype": w.dtype,
         "data": "synthetic",
         "config": {"workload": w.description, "name": w.name, "nx": p.nx, "nu": p.nu, "N": N, "K": K,
-                   "m": p.m, "n": p.n, "line_search_candidates": L, "jacobian": st.jacobian},
+                   "m": p.m, "n": p.n, "line_search_candidates": L, "jacobian": st.jacobian,
+                   "contraction": st.contraction},
         "sample_steps_per_s": args.steps * (K + 1 + L) * N / (ms_total * 1e-3),
         "host_wall_s": wall,
         "per_call": calls,

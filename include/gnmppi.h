@@ -82,6 +82,14 @@ extern "C" {
  * check is then reported in gnmppi_perturbation_gram's status word and this
  * call writes GNMPPI_OK to its own. */
 #define GNMPPI_JAC_GRAM_READY 0x100
+/* Flags for GNMPPI_F32 (either method): form S = dR W^T on the BF16 MFMA with
+ * FP32 accumulation.  BF16 rounds dR and W to bf16 (about 2^-9 relative per
+ * product: the "precision split").  BF16X3 splits each operand into hi + lo
+ * bf16 parts and sums the three leading products, which keeps FP32-level
+ * error (about 1e-6 relative on J at the c2 size) at the BF16 MFMA rate.  G
+ * stays on the FP32 contraction.  The two flags are mutually exclusive. */
+#define GNMPPI_JAC_BF16 0x200
+#define GNMPPI_JAC_BF16X3 0x400
 
 /* Problem data (Sec. 2).  Vectors are device arrays of the problem's dtype. */
 typedef struct gnmppi_problem {

@@ -378,7 +378,13 @@ JacPlan jacobian_plan(int dtype, int m, int n, int K, int method) {
   p.s_off = p.ginv_off + align_up(static_cast<size_t>(n) * p.npad * esz);
   split_plan(n, K, step, p.gsplit, p.gsplit_len);
   p.gpart_off = p.s_off + align_up(static_cast<size_t>(m) * p.npad * esz);
-  p.total = p.gpart_off + align_up(static_cast<size_t>(p.gsplit) * n * p.npad * esz);
+  p.kpad = (K + 31) / 32 * 32;
+  p.bf16_off = p.gpart_off + align_up(static_cast<size_t>(p.gsplit) * n * p.npad * esz);
+  p.total = p.bf16_off + (dtype == GNMPPI_F32 ? align_up(static_cast<size_t>(2) * n * p.kpad * 2) : 0);
+  if (method & (GNMPPI_JAC_BF16 | GNMPPI_JAC_BF16X3)) {
+    p.rows = m;  // G is formed by the FP32 W-only contraction
+    split_plan(m, K, 32, p.nsplit, p.split_len);
+  }
   return p;
 }
 
@@ -423,14 +429,34 @@ hipError_t jacobian_typed(int m, int n, int K, const T* R, int64_t ldr, const T*
   const JacPlan pl = jacobian_plan(dtype, m, n, K, method);
   const int base = method & 0xff;
   const bool ready = (method & GNMPPI_JAC_GRAM_READY) != 0;
+  const int bf16_terms = (method & GNMPPI_JAC_BF16X3) ? 3 : (method & GNMPPI_JAC_BF16) ? 1 : 0;
   char* wk = static_cast<char*>(work);
   T* part = reinterpret_cast<T*>(wk);
   const int64_t split_stride = static_cast<int64_t>(pl.rows) * pl.npad;
-  // S = (R - r0 1^T) W^T and (LS, unless ready) G = W W^T, as k-split partial sums
-  ContractArgs<T> c1{m, pl.rows, n, K, R, ldr, r0, W, ldw, W, ldw, pl.split_len,
-                     part, pl.npad, split_stride, pl.npad};
-  hipError_t e = launch_contract(c1, pl.nsplit, st);
-  if (e != hipSuccess) return e;
+  hipError_t e;
+  if constexpr (sizeof(T) == 4) {
+    if (bf16_terms) {
+      // S on the BF16 MFMA; G (LS) on the FP32 W-only contraction
+      __bf16* hi = reinterpret_cast<__bf16*>(wk + pl.bf16_off);
+      __bf16* lo = hi + static_cast<size_t>(n) * pl.kpad;
+      e = launch_split_bf16(n, K, pl.kpad, W, ldw, hi, lo, st);
+      if (e != hipSuccess) return e;
+      e = launch_contract_bf16(bf16_terms, m, n, K, R, ldr, r0, hi, lo, pl.kpad, pl.nsplit,
+                               pl.split_len, part, pl.npad, st);
+      if (e != hipSuccess) return e;
+      if (base == GNMPPI_JAC_LS && !ready) {
+        e = gram_typed<T>(m, n, K, W, ldw, work, status, st);
+        if (e != hipSuccess) return e;
+      }
+    }
+  }
+  if (!bf16_terms) {
+    // S = (R - r0 1^T) W^T and (LS, unless ready) G = W W^T, as k-split partial sums
+    ContractArgs<T> c1{m, pl.rows, n, K, R, ldr, r0, W, ldw, W, ldw, pl.split_len,
+                       part, pl.npad, split_stride, pl.npad};
+    e = launch_contract(c1, pl.nsplit, st);
+    if (e != hipSuccess) return e;
+  }
   const dim3 rgrid((n + 63) / 64, (m + 3) / 4);
   if (base == GNMPPI_JAC_MC) {
     // MC has no factorisation that can fail: the reduction reports success
@@ -441,7 +467,7 @@ hipError_t jacobian_typed(int m, int n, int K, const T* R, int64_t ldr, const T*
   }
   T* Ginv = reinterpret_cast<T*>(wk + pl.ginv_off);
   T* S = reinterpret_cast<T*>(wk + pl.s_off);
-  if (!ready) {
+  if (!ready && !bf16_terms) {
     e = gram_inverse_typed<T>(pl, n, K, W, ldw, wk, part, pl.nsplit, split_stride, m, status, st);
     if (e != hipSuccess) return e;
   }

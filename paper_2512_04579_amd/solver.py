@@ -105,6 +105,9 @@ class GNMPPI:
         self.work_j = _workspace(_lib.gnmppi_jacobian_workspace(code, m, n, K), dev)
         self.work_g = _workspace(_lib.gnmppi_ggn_workspace(code, m, n), dev)
         self.method = _lib.JAC_LS if settings.jacobian == "ls" else _lib.JAC_MC
+        if dt == torch.float32:
+            self.method |= {"native": 0, "bf16x3": _lib.JAC_BF16X3,
+                            "bf16": _lib.JAC_BF16}[settings.contraction]
 
     def sigma(self, it: int) -> float:
         s = self.s

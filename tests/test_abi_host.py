@@ -122,7 +122,13 @@ def test_other_entry_points_reject_bad_arguments():
                                            1 | _lib.JAC_GRAM_READY, 0.1, 0x400, 100, 0x1000, ws, None,
                                            None) == _lib.EINVAL  # gram flag only for LS
     assert lib.gnmppi_reconstruct_jacobian(_lib.F32, 3300, 100, 4096, 0x100, 4096, 0x200, 0x300, 4096,
-                                           0x200, 0.1, 0x400, 100, 0x1000, ws, None, None) == _lib.EINVAL
+                                           0x800, 0.1, 0x400, 100, 0x1000, ws, None, None) == _lib.EINVAL
+    wsd = lib.gnmppi_jacobian_workspace(_lib.F64, 3300, 100, 4096)
+    assert lib.gnmppi_reconstruct_jacobian(_lib.F64, 3300, 100, 4096, 0x100, 4096, 0x200, 0x300, 4096,
+                                           _lib.JAC_BF16, 0.0, 0x400, 100, 0x1000, wsd, None, None) == _lib.EINVAL
+    assert lib.gnmppi_reconstruct_jacobian(_lib.F32, 3300, 100, 4096, 0x100, 4096, 0x200, 0x300, 4096,
+                                           _lib.JAC_BF16 | _lib.JAC_BF16X3, 0.0, 0x400, 100, 0x1000, ws,
+                                           None, None) == _lib.EINVAL
     assert lib.gnmppi_perturbation_gram(_lib.F32, 3300, 100, 4096, 0x300, 4095, 0x1000, ws, None, None) == _lib.EINVAL
     assert lib.gnmppi_perturbation_gram(_lib.F32, 3300, 100, 4096, 0x300, 4096, 0x1000, ws - 1, None, None) == _lib.ENOSPACE
     wg = lib.gnmppi_ggn_workspace(_lib.F64, 120, 40)

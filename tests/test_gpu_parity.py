@@ -271,6 +271,28 @@ def test_perturbation_gram_reports_rank_deficiency():
     assert int(st.item()) == _lib.ERANK
 
 
+@pytest.mark.parametrize("case", ["c2", "chain_f32_ragged"])
+@pytest.mark.parametrize("method", ["ls", "mc"])
+def test_jacobian_bf16x3_split_keeps_fp32_accuracy(case, method):
+    prob, dtype, K, sigma, R, W = _jacobian_inputs(case)
+    code = (_lib.JAC_LS if method == "ls" else _lib.JAC_MC) | _lib.JAC_BF16X3
+    J, st = _run_jacobian(R, W, dtype, code, sigma * sigma)
+    assert st == _lib.OK
+    ref = jacobian.ls(R, W) if method == "ls" else jacobian.mc(R, W, sigma * sigma)
+    e = assert_parity(J, ref, "f32", "J (bf16x3)")
+    assert e < 2e-5, e
+
+
+def test_jacobian_bf16_precision_split_error_is_bounded():
+    # plain BF16 operands: the error is the precision split's, reported, not FP32 parity
+    prob, dtype, K, sigma, R, W = _jacobian_inputs("c2")
+    J, st = _run_jacobian(R, W, dtype, _lib.JAC_LS | _lib.JAC_BF16)
+    assert st == _lib.OK
+    e = rel_err(J, jacobian.ls(R, W))
+    print(f"BF16 precision split: J normwise relative error vs FP64 oracle {e:.3e}")
+    assert 1e-5 < e < 3e-3, e
+
+
 def test_jacobian_unaligned_leading_dimensions_take_the_scalar_path():
     prob, dtype, K, sigma, R, W = _jacobian_inputs("chain_f64_ragged")
     J, st = _run_jacobian(R, W, dtype, ldw=K + 1, ldr=K + 3)

@@ -79,6 +79,10 @@ class SolverSettings:
     lm_lambda: float = 0.0
     antithetic: bool = True
     jacobian: str = "ls"  # "ls" (default reading) or "mc" (literal Eq. (10))
+    # precision of the S = dR W^T contraction for float32 workloads: "native"
+    # (FP32 MFMA), "bf16x3" (hi/lo BF16 split, FP32-level error) or "bf16"
+    # (the precision split: BF16 operands, FP32 accumulation)
+    contraction: str = "native"
     temperature: float = 1.0  # MPPI lambda_k for the plain-MPPI comparator
     mppi_sigma0: float = 0.0  # plain-MPPI sampling scale (0 -> sigma0)
     mppi_beta: float = 1.0
@@ -154,7 +158,7 @@ def c2() -> Workload:
     prob, x0 = chain_problem(n_masses=16, N=50, dt=0.05, seed=0)
     st = SolverSettings(iters=50, K=4096, sigma0=0.3, beta=0.9, sigma_min=1e-3,
                         gamma=0.5, n_alpha=16, temperature=0.05, mppi_sigma0=0.3,
-                        mppi_beta=0.98)
+                        mppi_beta=0.98, contraction="bf16x3")
     return Workload("c2", prob, x0, st, "f32",
                     "chain16 cubic springs RK4 nx=64 nu=2 dt=0.05 N=50 K=4096 sigma=0.3 fp32")
 
@@ -162,7 +166,7 @@ def c2() -> Workload:
 def c4() -> Workload:
     prob, x0 = chain_problem(n_masses=16, N=66, dt=0.05, seed=0)
     st = SolverSettings(iters=50, K=8192, sigma0=0.3, beta=0.9, sigma_min=1e-3,
-                        gamma=0.5, n_alpha=16)
+                        gamma=0.5, n_alpha=16, contraction="bf16")
     return Workload("c4", prob, x0, st, "f32",
                     "chain16 RK4 N=66 m=4356 n=132 K=8192 precision split")
 
