@@ -4,14 +4,14 @@
 //  * reduce_sym_kernel -- adds the k-split / row-chunk partial sums of a
 //      symmetric matrix (lower triangle) into a full symmetric double matrix,
 //      one block per row so that every partial load is in flight at once.
-//  * sweep_kernel<TD, R> -- one workgroup of TD x TD = 16 x 16 threads sweeps an SPD matrix
+//  * sweep_kernel<R> -- one workgroup of 16 x 16 threads sweeps an SPD matrix
 //      with the symmetric sweep operator (Gauss-Jordan elimination without
 //      pivoting; for an SPD matrix its pivots are the Cholesky pivots
 //      squared).  Thread (ty, tx) keeps the lower-triangle elements
-//      (ty + TD r, tx + TD c), c <= r < R, in registers; each pivot
-//      broadcasts one column through LDS (double-buffered, so one barrier --
-//      or, for a single wave, one LDS fence -- per pivot) and every thread
-//      updates its own elements.
+//      (ty + 16 r, tx + 16 c), c <= r < R, in registers.  Pivots go in
+//      blocks of 16: each wave sweeps the 16 x 16 pivot block on its own
+//      (cross-lane shuffles, no barrier), then one rank-16 update per block
+//      brings every element up to date -- three barriers per 16 pivots.
 //      Sweeping pivots 0..n-1 of [[H, g], [g^T, c]] leaves -H^{-1} in the
 //      leading block and H^{-1} g in the last row: the same kernel yields
 //      G^{-1} for the LS Jacobian and the GGN direction -(H^{-1} g) with no
@@ -63,9 +63,12 @@ __global__ void __launch_bounds__(256) reduce_sym_kernel(const TP* __restrict__ 
   out[static_cast<int64_t>(j) * P + i] = s;
 }
 
-// ---- register-resident symmetric sweep ------------------------------------
+// ---- blocked register-resident symmetric sweep ------------------------------
 
 enum SweepOut { kSweepInverse = 0, kSweepDirection = 1 };
+
+constexpr int kSweepTD = 16;  // thread grid edge = pivots per block
+constexpr int kSweepLd = 18;  // LDS row stride (doubles): 16-byte rows, no bank conflicts
 
 // Reciprocal of an FP64 pivot: the hardware estimate refined by two
 // Newton-Raphson steps x <- x + x (1 - d x) (quadratic convergence; the
@@ -77,93 +80,170 @@ __device__ __forceinline__ double recip(double d) {
   return x;
 }
 
-// Orders the LDS column broadcast of one pivot: a block-wide barrier for a
-// multi-wave sweep, a wavefront fence for the single-wave variant (a wave
-// executes its LDS operations in order, so no s_barrier is needed).
-template <int TD>
-__device__ __forceinline__ void sweep_sync() {
-  if constexpr (TD * TD > kWave) {
-    __syncthreads();
-  } else {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// Orders LDS traffic between the lanes of one wave (a wave executes its LDS
+// operations in order, so no s_barrier is needed).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Cross-lane moves of an FP64 value: DPP row_newbcast (every lane reads lane
+// N of its 16-lane row) and a read of one lane into a uniform value.
+template <int N>
+__device__ __forceinline__ double row_bcast(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), 0x150 + N, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), 0x150 + N, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), lane);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), lane);
+  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+// The sweep over one pivot p is the rank-1 update A <- A_{\p} - z z^T / d
+// with d = A_pp, z = column p with its pivot entry replaced by -1, and
+// A_{\p} = A with row and column p zeroed.  For a block B of pivots the same
+// identity reads A <- A_{\B} - Z D^{-1} Z^T with D = A_BB and Z = A_{:,B}
+// whose rows in B are replaced by -I; sweeping B inside D alone gives
+// -D^{-1}.  diag_pivot<p> does one pivot of that on one wave: lane l holds
+// D[l % 16][4 (l / 16) + e], e < 4, so row p of the block is lane p of every
+// 16-lane row (a DPP broadcast), the pivot one lane (a readlane) and column
+// p one shuffle.  Branch-free: pivots p >= nbv leave D as it is and a pivot
+// at or below tol clears `ok`.
+template <int p>
+__device__ __forceinline__ void diag_pivot(double (&d4)[4], int nbv, double tol, bool& ok, int li,
+                                           int lg) {
+  constexpr int gp = p >> 2, ep = p & 3;
+  const bool act = p < nbv;  // uniform
+  const double d = read_lane(d4[ep], p + 16 * gp);
+  ok = ok && (!act || d > tol);
+  const double inv = recip(d);
+  double zi = __shfl(d4[ep], li + 16 * gp, kWave);  // D[li][p]
+  double zj[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) zj[e] = row_bcast<p>(d4[e]);  // D[p][4 lg + e]
+  if (li == p) zi = -1.0;
+  const double sr = act ? -zi * inv : 0.0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const bool pc = 4 * lg + e == p;
+    const double a = (act && (li == p || pc)) ? 0.0 : d4[e];
+    d4[e] = fma(sr, pc ? -1.0 : zj[e], a);
   }
 }
 
-// One pivot p = TD PB + pm of the sweep, written as a single rank-1 update:
-// with c = column p, d = c_p and z = c - (d + 1) e_p (c with its pivot entry
-// replaced by -1), the swept matrix is A_{\p} - z z^T / d, where A_{\p} is A
-// with row and column p set to zero.  The TD x TD threads own elements
-// (ty + TD r, tx + TD c), c <= r < R.  PB is a compile-time column block, so
-// every register index is static and only the PB row / column blocks select.
-template <int TD, int R, int PB>
-__device__ __forceinline__ bool sweep_pivot(double (&A)[R][R], double* __restrict__ cv, int P,
-                                            int pm, int tx, int ty, double tol) {
-  const int p = TD * PB + pm;
-  const bool col_owner = tx == pm, row_owner = ty == pm;
-  // publish column p: rows >= TD PB from column block PB, rows < TD PB from row p
-  if (col_owner) {
+template <int p>
+__device__ __forceinline__ void diag_pivots(double (&d4)[4], int nbv, double tol, bool& ok, int li,
+                                            int lg) {
+  if constexpr (p < 16) {
+    diag_pivot<p>(d4, nbv, tol, ok, li, lg);
+    diag_pivots<p + 1>(d4, nbv, tol, ok, li, lg);
+  }
+}
+
+// Pivot block PB (pivots 16 PB .. 16 PB + nbv - 1).  The TD x TD threads own
+// elements (ty + TD r, tx + TD c), c <= r < R, of the lower triangle.
+//  1. the block's 16 columns (all rows) go to LDS `pan`;
+//  2. every wave sweeps the 16 x 16 diagonal block itself -> D^{-1};
+//  3. Y = Z D^{-1} (rows x 16) into LDS `ybuf`;
+//  4. each thread applies A_{\B} - Y Z^T to its own elements.
+// Padding rows and columns (index >= P) start at zero and stay zero: their
+// pan and ybuf rows are zero, so no step needs a bounds guard.
+template <int R, int PB>
+__device__ __forceinline__ bool sweep_blocks(double (&A)[R][R], double* __restrict__ pan,
+                                             double* __restrict__ ybuf, double* __restrict__ dinv,
+                                             int npiv, int tx, int ty, double tol) {
+  constexpr int TD = kSweepTD, LD = kSweepLd;
+  if constexpr (PB < R) {
+    const int nbv = min(TD, npiv - TD * PB);
+#pragma unroll
+    for (int r = PB; r < R; ++r) pan[(ty + TD * r) * LD + tx] = A[r][PB];
+#pragma unroll
+    for (int c = 0; c < PB; ++c) pan[(tx + TD * c) * LD + ty] = A[PB][c];
+    __syncthreads();
+
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int li = lane & 15, lg = lane >> 4;
+    double d4[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) d4[e] = pan[(TD * PB + li) * LD + 4 * lg + e];
+    bool ok = true;
+    diag_pivots<0>(d4, nbv, tol, ok, li, lg);
+    if (!ok) return false;  // the same pivots in every wave: uniform
+    double* dw = dinv + wave * TD * LD;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = 4 * lg + e;
+      dw[li * LD + k] = (li < nbv && k < nbv) ? -d4[e] : 0.0;
+    }
+    wave_lds_sync();
+
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int i = ty + TD * q;
+      double y = 0.0;
+#pragma unroll
+      for (int l = 0; l < TD; ++l) y = fma(pan[i * LD + l], dw[l * LD + tx], y);
+      if (q == PB) y = ty < nbv ? -dw[ty * LD + tx] : y;  // rows in B: Z_i = -e_i
+      ybuf[i * LD + tx] = y;
+    }
+    __syncthreads();
+
+    constexpr int KC = R > 8 ? 2 : 4;  // k-values per pass: bounds the live Y / Z registers
+#pragma unroll 1
+    for (int k0 = 0; k0 < TD; k0 += KC) {
+      double yv[R][KC], zv[R][KC];
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int e = 0; e < KC; ++e) {
+          yv[r][e] = ybuf[(ty + TD * r) * LD + k0 + e];
+          zv[r][e] = pan[(tx + TD * r) * LD + k0 + e];
+        }
+      const bool clear_row = k0 == 0 && ty < nbv;  // rows in B start from A_{\B} = 0
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c <= r; ++c) {
+          double a = A[r][c];
+          if (r == PB) a = clear_row ? 0.0 : a;
+#pragma unroll
+          for (int e = 0; e < KC; ++e) a = fma(-yv[r][e], zv[c][e], a);
+          A[r][c] = a;
+        }
+    }
+    // columns in B: Z_j = -e_j, so the new element is Y[i][j - 16 PB]
 #pragma unroll
     for (int r = PB; r < R; ++r) {
-      const int i = ty + TD * r;
-      if (i < P) cv[i] = A[r][PB];
+      const double y = ybuf[(ty + TD * r) * LD + tx];
+      A[r][PB] = tx < nbv ? y : A[r][PB];
     }
-  }
-  if (row_owner) {
-#pragma unroll
-    for (int c = 0; c < PB; ++c) cv[tx + TD * c] = A[PB][c];
-  }
-  sweep_sync<TD>();
-  const double d = cv[p];
-  if (!(d > tol)) return false;  // the same pivot in every thread: uniform
-  const double inv = recip(d);
-  double zi[R], zj[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int i = ty + TD * r, j = tx + TD * r;
-    zi[r] = i < P ? cv[i] : 0.0;
-    zj[r] = j < P ? cv[j] : 0.0;
-  }
-  if (row_owner) zi[PB] = -1.0;
-  if (col_owner) zj[PB] = -1.0;
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const double sr = -zi[r] * inv;
-#pragma unroll
-    for (int c = 0; c <= r; ++c) {
-      double a = A[r][c];
-      if (r == PB && row_owner) a = 0.0;
-      if (c == PB && col_owner) a = 0.0;
-      A[r][c] = fma(sr, zj[c], a);
-    }
+    __syncthreads();
+    if (TD * (PB + 1) < npiv) return sweep_blocks<R, PB + 1>(A, pan, ybuf, dinv, npiv, tx, ty, tol);
   }
   return true;
 }
 
-template <int TD, int R, int PB>
-__device__ __forceinline__ bool sweep_block(double (&A)[R][R], double (*colv)[TD * R], int P,
-                                            int npiv, int tx, int ty, double tol) {
-  if constexpr (PB < R) {
-    const int pend = min(TD, npiv - TD * PB);
-    for (int pm = 0; pm < pend; ++pm)
-      if (!sweep_pivot<TD, R, PB>(A, colv[(TD * PB + pm) & 1], P, pm, tx, ty, tol)) return false;
-    if (TD * (PB + 1) < npiv) return sweep_block<TD, R, PB + 1>(A, colv, P, npiv, tx, ty, tol);
-  }
-  return true;
-}
-
-template <int TD, int R, typename TO>
-__global__ void __launch_bounds__(TD * TD) sweep_kernel(const double* __restrict__ M, int P,
-                                                        int npiv, int mode,
-                                                        TO* __restrict__ inv_out, int64_t ldo,
-                                                        TO* __restrict__ dir_out, int32_t* status,
-                                                        int fail_code) {
-  constexpr int kWaves = (TD * TD + kWave - 1) / kWave;
-  __shared__ double colv[2][TD * R];
+template <int R, typename TO>
+__global__ void __launch_bounds__(kSweepTD * kSweepTD) sweep_kernel(
+    const double* __restrict__ M, int P, int npiv, int mode, TO* __restrict__ inv_out, int64_t ldo,
+    TO* __restrict__ dir_out, int32_t* status, int fail_code) {
+  constexpr int TD = kSweepTD, LD = kSweepLd;
+  constexpr int kWaves = TD * TD / kWave;
+  __shared__ double pan[TD * R * LD];
+  __shared__ double ybuf[TD * R * LD];
+  __shared__ double dinv[kWaves * TD * LD];
   __shared__ double wmax[kWaves];
   __shared__ double tol_s;
   const int tx = threadIdx.x % TD, ty = threadIdx.x / TD;
+  for (int e = threadIdx.x; e < TD * R * LD; e += TD * TD) {
+    pan[e] = 0.0;
+    ybuf[e] = 0.0;
+  }
   double A[R][R];  // only c <= r is used
 #pragma unroll
   for (int r = 0; r < R; ++r)
@@ -187,7 +267,7 @@ __global__ void __launch_bounds__(TD * TD) sweep_kernel(const double* __restrict
     tol_s = static_cast<double>(npiv) * 0x1.0p-52 * mx;
   }
   __syncthreads();
-  const bool ok = sweep_block<TD, R, 0>(A, colv, P, npiv, tx, ty, tol_s);
+  const bool ok = npiv <= 0 || sweep_blocks<R, 0>(A, pan, ybuf, dinv, npiv, tx, ty, tol_s);
   if (mode == kSweepInverse) {
     if (ok)
 #pragma unroll
@@ -215,17 +295,15 @@ __global__ void __launch_bounds__(TD * TD) sweep_kernel(const double* __restrict
   if (threadIdx.x == 0 && status) *status = ok ? GNMPPI_OK : fail_code;
 }
 
-// 16 x 16 threads (one wave per SIMD); R = ceil(P / 16) <= 13 for P <= 208.
-// Measured at P = 101: 8 x 8 lanes (one wave, no barrier) is issue-bound and
-// 2.5x slower, 32 x 32 threads 15% slower.
+// One workgroup of 16 x 16 threads; R = ceil(P / 16) <= 13 for P <= 208.
 template <typename TO>
 hipError_t launch_sweep(int P, int npiv, int mode, const double* M, TO* inv_out, int64_t ldo,
                         TO* dir_out, int32_t* status, int fail_code, hipStream_t st) {
-  const int R = (P + 15) / 16;
-#define GNM_SWEEP_CASE(RR)                                                                      \
-  case RR:                                                                                      \
-    hipLaunchKernelGGL((sweep_kernel<16, RR, TO>), dim3(1), dim3(256), 0, st, M, P, npiv, mode, \
-                       inv_out, ldo, dir_out, status, fail_code);                               \
+  const int R = (P + kSweepTD - 1) / kSweepTD;
+#define GNM_SWEEP_CASE(RR)                                                                       \
+  case RR:                                                                                       \
+    hipLaunchKernelGGL((sweep_kernel<RR, TO>), dim3(1), dim3(kSweepTD * kSweepTD), 0, st, M, P,  \
+                       npiv, mode, inv_out, ldo, dir_out, status, fail_code);                    \
     break;
   switch (R) {
     GNM_SWEEP_CASE(1) GNM_SWEEP_CASE(2) GNM_SWEEP_CASE(3) GNM_SWEEP_CASE(4) GNM_SWEEP_CASE(5)
@@ -343,16 +421,34 @@ hipError_t launch_gram(int nt, int nblocks, hipStream_t st, int m, int n, const 
 
 // k-split plan: enough slices that ~1.5k waves (16 rows each) cover the
 // machine, at least two MFMA k-steps per slice.
-static void split_plan(int rows, int K, int step, int& nsplit_out, int& split_len_out) {
-  const int waves_per_split = (rows + 15) / 16;
+// k-split of a contraction over `rows` output rows: every wave owns a 16-row
+// tile and one of the kw step sequences of a slice; aim at ~4k waves (4 per
+// SIMD) with at least two steps per wave and steps spread evenly.
+static void split_plan(int rows, int K, int step, int kw, int& nsplit_out, int& split_len_out) {
+  const int waves_per_split = (rows + 15) / 16 * kw;
   const int ksteps = (K + step - 1) / step;
-  int nsplit = (1536 + waves_per_split - 1) / waves_per_split;
-  const int max_split = ksteps / 2 > 1 ? ksteps / 2 : 1;
+  int nsplit = (4096 + waves_per_split - 1) / waves_per_split;
+  const int max_split = ksteps / (2 * kw) > 1 ? ksteps / (2 * kw) : 1;
+  if (nsplit > max_split) nsplit = max_split;
+  if (nsplit < 1) nsplit = 1;
+  int steps_per_split = (ksteps + nsplit - 1) / nsplit;
+  steps_per_split = (steps_per_split + kw - 1) / kw * kw;
+  nsplit_out = (ksteps + steps_per_split - 1) / steps_per_split;
+  split_len_out = steps_per_split * step;
+}
+
+// k-split of the BF16 contraction: blocks of 64 kBf16RowTiles rows; aim at
+// two blocks per CU with at least four k-steps per block.
+static void bf16_split_plan(int m, int K, int& nsplit_out, int& split_len_out) {
+  const int row_blocks = (m + 64 * kBf16RowTiles - 1) / (64 * kBf16RowTiles);
+  const int ksteps = (K + 31) / 32;
+  int nsplit = (768 + row_blocks - 1) / row_blocks;
+  const int max_split = ksteps / 4 > 1 ? ksteps / 4 : 1;
   if (nsplit > max_split) nsplit = max_split;
   if (nsplit < 1) nsplit = 1;
   const int steps_per_split = (ksteps + nsplit - 1) / nsplit;
   nsplit_out = (ksteps + steps_per_split - 1) / steps_per_split;
-  split_len_out = steps_per_split * step;
+  split_len_out = steps_per_split * 32;
 }
 
 JacPlan jacobian_plan(int dtype, int m, int n, int K, int method) {
@@ -363,27 +459,31 @@ JacPlan jacobian_plan(int dtype, int m, int n, int K, int method) {
   p.npad = 16 * p.ncol_tiles;
   const int base = method & 0xff;
   const bool ready = (method & GNMPPI_JAC_GRAM_READY) != 0;
+  const int kw = contract_kw(esz, n);
   p.rows = m + ((base == GNMPPI_JAC_LS && !ready) ? n : 0);
-  split_plan(p.rows, K, step, p.nsplit, p.split_len);
-  // the partial-sum area is sized for the largest row set (m + n) so that
-  // every method shares one workspace layout
-  int ns_max, sl_max;
-  split_plan(m + n, K, step, ns_max, sl_max);
-  int ns_m, sl_m;
-  split_plan(m, K, step, ns_m, sl_m);
-  const size_t part_elems = static_cast<size_t>(ns_max > ns_m ? ns_max : ns_m) * (m + n) * p.npad;
+  split_plan(p.rows, K, step, kw, p.nsplit, p.split_len);
+  // the partial-sum area is sized for the largest split count over the row
+  // sets of every method (m + n, m, and m on the BF16 kernel) so that all
+  // methods share one workspace layout
+  int ns_max, sl_max, ns_m, sl_m, ns_b = 0, sl_b;
+  split_plan(m + n, K, step, kw, ns_max, sl_max);
+  split_plan(m, K, step, kw, ns_m, sl_m);
+  if (dtype == GNMPPI_F32) bf16_split_plan(m, K, ns_b, sl_b);
+  if (ns_m > ns_max) ns_max = ns_m;
+  if (ns_b > ns_max) ns_max = ns_b;
+  const size_t part_elems = static_cast<size_t>(ns_max) * (m + n) * p.npad;
   p.part_bytes = align_up(part_elems * esz);
   p.gsum_off = p.part_bytes;
   p.ginv_off = p.gsum_off + align_up(static_cast<size_t>(n) * n * 8);
   p.s_off = p.ginv_off + align_up(static_cast<size_t>(n) * p.npad * esz);
-  split_plan(n, K, step, p.gsplit, p.gsplit_len);
+  split_plan(n, K, step, kw, p.gsplit, p.gsplit_len);
   p.gpart_off = p.s_off + align_up(static_cast<size_t>(m) * p.npad * esz);
   p.kpad = (K + 31) / 32 * 32;
   p.bf16_off = p.gpart_off + align_up(static_cast<size_t>(p.gsplit) * n * p.npad * esz);
   p.total = p.bf16_off + (dtype == GNMPPI_F32 ? align_up(static_cast<size_t>(2) * n * p.kpad * 2) : 0);
   if (method & (GNMPPI_JAC_BF16 | GNMPPI_JAC_BF16X3)) {
     p.rows = m;  // G is formed by the FP32 W-only contraction
-    split_plan(m, K, 32, p.nsplit, p.split_len);
+    bf16_split_plan(m, K, p.nsplit, p.split_len);
   }
   return p;
 }

@@ -75,32 +75,75 @@ __device__ __forceinline__ void load_lane_k(const T* __restrict__ p, int kl, int
   }
 }
 
-template <typename T, int TM, int NT, bool VEC>
+// Epilogue shared by the contraction kernels.  Block = 4 waves = (4 / KW)
+// row tiles of 16 rows, each worked by KW waves that take turns over the
+// slice's k-steps (wave kw owns steps kw, kw + KW, ...).  With KW > 1 every
+// wave parks its accumulators in LDS and the tile's 64 KW threads add the KW
+// partial tiles in a fixed order (reproducible) and store whole rows
+// (coalesced); with KW = 1 each lane stores its accumulators directly.
+template <typename T, typename Acc, int NT, int KW, typename OutRow>
+__device__ __forceinline__ void store_tiles(const Acc (&acc)[NT], T* __restrict__ lds, int row_base,
+                                            int rows, T* __restrict__ out, int64_t ldo, int ocols,
+                                            OutRow out_row) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int r16 = lane & 15, kq = lane >> 4;
+  if constexpr (KW == 1) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = row_base + out_row(kq, j);
+      if (row < rows)
+#pragma unroll
+        for (int tn = 0; tn < NT; ++tn) {
+          const int col = 16 * tn + r16;
+          if (col < ocols) out[row * ldo + col] = acc[tn][j];
+        }
+    }
+  } else {
+    constexpr int LD = 16 * NT + 1;  // odd stride: lane groups land on distinct banks
+    T* mine = lds + wave * 16 * LD;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int tn = 0; tn < NT; ++tn) mine[out_row(kq, j) * LD + 16 * tn + r16] = acc[tn][j];
+    __syncthreads();
+    const int rt = wave / KW, t = threadIdx.x - rt * KW * kWave;
+    const T* tile = lds + rt * KW * 16 * LD;
+    for (int e = t; e < 16 * 16 * NT; e += KW * kWave) {
+      const int r = e / (16 * NT), c = e - r * (16 * NT);
+      const int row = row_base + r;
+      if (row < rows && c < ocols) {
+        T v = tile[r * LD + c];
+#pragma unroll
+        for (int w = 1; w < KW; ++w) v += tile[w * 16 * LD + r * LD + c];
+        out[row * ldo + c] = v;
+      }
+    }
+  }
+}
+
+template <typename T, int NT, bool VEC, int KW>
 __global__ void __launch_bounds__(256) contract_kernel(ContractArgs<T> a) {
   using MT = Mfma<T>;
   using Acc = typename MT::Acc;
   constexpr int V = MT::kLaneK, STEP = MT::kStep;
+  extern __shared__ unsigned char contract_smem[];
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int r16 = lane & 15, kq = lane >> 4;
-  const int row_base = (blockIdx.x * 4 + wave) * 16 * TM;
+  const int row_base = (blockIdx.x * (4 / KW) + wave / KW) * 16;
+  const int kw = wave % KW;
   const int kbeg = blockIdx.y * a.split_len;
   const int kend = min(a.K, kbeg + a.split_len);
 
-  const T* arow[TM];
-  T asub[TM];
-#pragma unroll
-  for (int tm = 0; tm < TM; ++tm) {
-    const int row = row_base + 16 * tm + r16;
-    if (row < a.m) {
-      arow[tm] = a.A + row * a.lda;
-      asub[tm] = a.asub ? a.asub[row] : T(0);
-    } else if (row < a.rows) {
-      arow[tm] = a.A2 + (row - a.m) * a.lda2;
-      asub[tm] = 0;
-    } else {  // past the last row: read a valid row, never stored
-      arow[tm] = a.B;
-      asub[tm] = 0;
-    }
+  const int row = row_base + r16;
+  const T* arow;
+  T asub = 0;
+  if (row < a.m) {
+    arow = a.A + row * a.lda;
+    asub = a.asub ? a.asub[row] : T(0);
+  } else if (row < a.rows) {
+    arow = a.A2 + (row - a.m) * a.lda2;
+  } else {  // past the last row: read a valid row, never stored
+    arow = a.B;
   }
   const T* bcol[NT];
   bool bzero[NT];
@@ -111,23 +154,18 @@ __global__ void __launch_bounds__(256) contract_kernel(ContractArgs<T> a) {
     bzero[tn] = col >= a.ncol;
   }
 
-  Acc acc[TM][NT];
+  Acc acc[NT];
 #pragma unroll
-  for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-    for (int tn = 0; tn < NT; ++tn) acc[tm][tn] = Acc{0, 0, 0, 0};
+  for (int tn = 0; tn < NT; ++tn) acc[tn] = Acc{0, 0, 0, 0};
 
   if (row_base < a.rows) {
-    for (int k0 = kbeg; k0 < kend; k0 += STEP) {
+    for (int k0 = kbeg + kw * STEP; k0 < kend; k0 += KW * STEP) {
       const bool full = k0 + STEP <= kend;
       const int kl = k0 + kq * V;
-      T av[TM][V], bv[NT][V];
+      T av[V], bv[NT][V];
+      load_lane_k<T, VEC>(arow, kl, kend, full, av);
 #pragma unroll
-      for (int tm = 0; tm < TM; ++tm) {
-        load_lane_k<T, VEC>(arow[tm], kl, kend, full, av[tm]);
-#pragma unroll
-        for (int t = 0; t < V; ++t) av[tm][t] = (kl + t < kend) ? av[tm][t] - asub[tm] : T(0);
-      }
+      for (int t = 0; t < V; ++t) av[t] = (kl + t < kend) ? av[t] - asub : T(0);
 #pragma unroll
       for (int tn = 0; tn < NT; ++tn) {
         load_lane_k<T, VEC>(bcol[tn], kl, kend, full, bv[tn]);
@@ -138,32 +176,26 @@ __global__ void __launch_bounds__(256) contract_kernel(ContractArgs<T> a) {
 #pragma unroll
       for (int t = 0; t < V; ++t)
 #pragma unroll
-        for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-          for (int tn = 0; tn < NT; ++tn) acc[tm][tn] = MT::mma(av[tm][t], bv[tn][t], acc[tm][tn]);
+        for (int tn = 0; tn < NT; ++tn) acc[tn] = MT::mma(av[t], bv[tn][t], acc[tn]);
     }
   }
 
   T* out = a.out + static_cast<int64_t>(blockIdx.y) * a.split_stride;
-#pragma unroll
-  for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = row_base + 16 * tm + MT::out_row(kq, j);
-      if (row < a.rows)
-#pragma unroll
-        for (int tn = 0; tn < NT; ++tn) {
-          const int col = 16 * tn + r16;
-          if (col < a.ocols) out[row * a.ldo + col] = acc[tm][tn][j];
-        }
-    }
+  store_tiles<T, Acc, NT, KW>(acc, reinterpret_cast<T*>(contract_smem), row_base, a.rows, out,
+                              a.ldo, a.ocols, [](int q, int j) { return MT::out_row(q, j); });
 }
 
-template <typename T, int TM, bool VEC>
+template <typename T, int NT>
+constexpr size_t split_lds_bytes() {
+  return static_cast<size_t>(4) * 16 * (16 * NT + 1) * sizeof(T);
+}
+
+template <typename T, bool VEC, int KW>
 hipError_t contract_dispatch_nt(int nt, dim3 grid, hipStream_t st, const ContractArgs<T>& a) {
 #define GNM_NT_CASE(NT)                                                                       \
   case NT:                                                                                    \
-    hipLaunchKernelGGL((contract_kernel<T, TM, NT, VEC>), grid, dim3(256), 0, st, a);         \
+    hipLaunchKernelGGL((contract_kernel<T, NT, VEC, KW>), grid, dim3(256),                    \
+                       (KW > 1 ? split_lds_bytes<T, NT>() : size_t{0}), st, a);               \
     break;
   switch (nt) {
     GNM_NT_CASE(1) GNM_NT_CASE(2) GNM_NT_CASE(3) GNM_NT_CASE(4) GNM_NT_CASE(5) GNM_NT_CASE(6)
@@ -181,15 +213,20 @@ bool vec_ok(const T* p, int64_t ld) {
   return p == nullptr || ((ld % per) == 0 && (reinterpret_cast<uintptr_t>(p) % 16) == 0);
 }
 
-template <typename T>
-hipError_t contract_typed(const ContractArgs<T>& a, int nsplit, hipStream_t st) {
-  constexpr int TM = 1;
-  const int row_blocks = (a.rows + 64 * TM - 1) / (64 * TM);
+template <typename T, int KW>
+hipError_t contract_kw_typed(const ContractArgs<T>& a, int nsplit, hipStream_t st) {
+  const int row_blocks = (a.rows + 64 / KW - 1) / (64 / KW);
   dim3 grid(row_blocks, nsplit);
   const int nt = (a.ncol + 15) / 16;
   const bool vec = vec_ok(a.A, a.lda) && vec_ok(a.A2, a.lda2) && vec_ok(a.B, a.ldb);
-  if (vec) return contract_dispatch_nt<T, TM, true>(nt, grid, st, a);
-  return contract_dispatch_nt<T, TM, false>(nt, grid, st, a);
+  if (vec) return contract_dispatch_nt<T, true, KW>(nt, grid, st, a);
+  return contract_dispatch_nt<T, false, KW>(nt, grid, st, a);
+}
+
+template <typename T>
+hipError_t contract_typed(const ContractArgs<T>& a, int nsplit, hipStream_t st) {
+  if (contract_kw(sizeof(T), a.ncol) == 4) return contract_kw_typed<T, 4>(a, nsplit, st);
+  return contract_kw_typed<T, 1>(a, nsplit, st);
 }
 
 // ---- BF16 MFMA contraction of the residual differences -----------------------
@@ -219,75 +256,159 @@ __global__ void __launch_bounds__(256) split_bf16_kernel(int K, int kpad, const 
   lo[static_cast<int64_t>(row) * kpad + k] = static_cast<__bf16>(v - static_cast<float>(h));
 }
 
-template <int TERMS, int NT, bool VEC>
+// Block = 4 waves over 64 TM rows and one k-slice.  The B operand of each
+// 32-wide k-step (NT 16 columns, hi and lo planes) is copied once per block
+// into a double-buffered LDS stage and read by all four waves, so the L2 ->
+// CU traffic for B is a quarter of what per-wave loads would move; the LDS
+// stage is laid out [plane][k-group of 8][column] so that the 16 lanes of a
+// fragment read 256 contiguous bytes.  The A operand (fp32 residual rows)
+// streams from HBM into registers one step ahead and is converted to bf16
+// (and split into hi + lo) in registers.  One barrier per step.
+template <int TERMS, int NT, int TM, bool VEC>
 __global__ void __launch_bounds__(256) contract_bf16_kernel(
     int m, int n, int K, const float* __restrict__ R, int64_t ldr, const float* __restrict__ r0,
     const __bf16* __restrict__ Bh, const __bf16* __restrict__ Bl, int kpad, int split_len,
     float* __restrict__ part, int npad) {
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  constexpr int PLANES = TERMS == 3 ? 2 : 1;
+  constexpr int NCOL = 16 * NT;
+  constexpr int CHUNKS = PLANES * NCOL * (kBf16Step / 8);  // 16-byte pieces per stage
+  constexpr int PER_THREAD = (CHUNKS + 255) / 256;
+  __shared__ bf16x8 stage[2][PLANES][kBf16Step / 8][NCOL];
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wave = tid / kWave;
   const int r16 = lane & 15, kq = lane >> 4;
-  const int row_base = (blockIdx.x * 4 + wave) * 16;
+  const int row_base = blockIdx.x * 64 * TM + wave * 16 * TM;
   const int kbeg = blockIdx.y * split_len;
   const int kend = min(K, kbeg + split_len);
-  const int row = row_base + r16;
-  const float* arow = R + (row < m ? row : 0) * ldr;
-  const float asub = row < m ? r0[row] : 0.0f;
-  int64_t boff[NT];
-  bool bzero[NT];
+  const int nstep = (kend - kbeg + kBf16Step - 1) / kBf16Step;
+
+  const float* arow[TM];
+  float asub[TM];
 #pragma unroll
-  for (int tn = 0; tn < NT; ++tn) {
-    const int col = 16 * tn + r16;
-    boff[tn] = static_cast<int64_t>(col < n ? col : 0) * kpad;
-    bzero[tn] = col >= n;
+  for (int t = 0; t < TM; ++t) {
+    const int row = row_base + 16 * t + r16;
+    arow[t] = R + (row < m ? row : 0) * ldr;
+    asub[t] = row < m ? r0[row] : 0.0f;
   }
-  f32x4 acc[NT];
+  // the B pieces this thread copies: piece c -> (plane, column, k-group),
+  // k-group fastest so that 8 neighbouring threads read one 128-byte run
+  const __bf16* bsrc[PER_THREAD];
+  bool bvalid[PER_THREAD];
 #pragma unroll
-  for (int tn = 0; tn < NT; ++tn) acc[tn] = f32x4{0, 0, 0, 0};
-  if (row_base < m) {
-    for (int k0 = kbeg; k0 < kend; k0 += kBf16Step) {
-      const int kl = k0 + 8 * kq;
-      float a[8];
-      if (VEC && k0 + kBf16Step <= kend) {
-        const f32x4 x0 = *reinterpret_cast<const f32x4*>(arow + kl);
-        const f32x4 x1 = *reinterpret_cast<const f32x4*>(arow + kl + 4);
+  for (int i = 0; i < PER_THREAD; ++i) {
+    const int c = tid + 256 * i;
+    const int kg = c % (kBf16Step / 8), col = (c / (kBf16Step / 8)) % NCOL;
+    const int pl = c / (NCOL * (kBf16Step / 8));
+    bvalid[i] = c < CHUNKS && col < n;
+    bsrc[i] = (pl == 0 ? Bh : Bl) + static_cast<int64_t>(col < n ? col : 0) * kpad + 8 * kg;
+  }
+  auto load_b = [&](int k0, bf16x8 (&reg)[PER_THREAD]) {
+#pragma unroll
+    for (int i = 0; i < PER_THREAD; ++i)
+      reg[i] = bvalid[i] ? *reinterpret_cast<const bf16x8*>(bsrc[i] + k0) : bf16x8{};
+  };
+  auto store_b = [&](int buf, const bf16x8 (&reg)[PER_THREAD]) {
+#pragma unroll
+    for (int i = 0; i < PER_THREAD; ++i) {
+      const int c = tid + 256 * i;
+      if (c < CHUNKS) {
+        const int kg = c % (kBf16Step / 8), col = (c / (kBf16Step / 8)) % NCOL;
+        const int pl = c / (NCOL * (kBf16Step / 8));
+        stage[buf][pl][kg][col] = reg[i];
+      }
+    }
+  };
+  // this lane's 8 A values of row tile t for the step at k0, minus r0
+  auto load_a = [&](int k0, float (&a)[TM][8]) {
+    const int kl = k0 + 8 * kq;
+    if (VEC && k0 + kBf16Step <= kend) {
+#pragma unroll
+      for (int t = 0; t < TM; ++t) {
+        const f32x4 x0 = *reinterpret_cast<const f32x4*>(arow[t] + kl);
+        const f32x4 x1 = *reinterpret_cast<const f32x4*>(arow[t] + kl + 4);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          a[e] = x0[e];
-          a[4 + e] = x1[e];
+          a[t][e] = x0[e];
+          a[t][4 + e] = x1[e];
         }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) a[e] = (kl + e < kend) ? arow[kl + e] : 0.0f;
       }
-      bf16x8 ah, al;
+    } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float v = (kl + e < kend) ? a[e] - asub : 0.0f;
-        ah[e] = static_cast<__bf16>(v);
-        if constexpr (TERMS == 3) al[e] = static_cast<__bf16>(v - static_cast<float>(ah[e]));
+      for (int t = 0; t < TM; ++t)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a[t][e] = (kl + e < kend) ? arow[t][kl + e] : 0.0f;
+    }
+#pragma unroll
+    for (int t = 0; t < TM; ++t)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) a[t][e] = (kl + e < kend) ? a[t][e] - asub[t] : 0.0f;
+  };
+
+  f32x4 acc[TM][NT];
+#pragma unroll
+  for (int t = 0; t < TM; ++t)
+#pragma unroll
+    for (int tn = 0; tn < NT; ++tn) acc[t][tn] = f32x4{0, 0, 0, 0};
+
+  if (nstep > 0) {
+    bf16x8 breg[PER_THREAD];
+    float a[TM][8];
+    load_b(kbeg, breg);
+    load_a(kbeg, a);
+    store_b(0, breg);
+    __syncthreads();
+    for (int s = 0; s < nstep; ++s) {
+      const int k0 = kbeg + s * kBf16Step;
+      const bool more = s + 1 < nstep;
+      float an[TM][8];
+      if (more) {
+        load_b(k0 + kBf16Step, breg);
+        load_a(k0 + kBf16Step, an);
       }
+      const int buf = s & 1;
+      bf16x8 ah[TM], al[TM];
+#pragma unroll
+      for (int t = 0; t < TM; ++t)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          ah[t][e] = static_cast<__bf16>(a[t][e]);
+          if constexpr (TERMS == 3) al[t][e] = static_cast<__bf16>(a[t][e] - static_cast<float>(ah[t][e]));
+        }
 #pragma unroll
       for (int tn = 0; tn < NT; ++tn) {
-        bf16x8 bh = *reinterpret_cast<const bf16x8*>(Bh + boff[tn] + kl);
-        if (bzero[tn]) bh = bf16x8{};
-        acc[tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[tn], 0, 0, 0);
+        const bf16x8 bh = stage[buf][0][kq][16 * tn + r16];
+#pragma unroll
+        for (int t = 0; t < TM; ++t)
+          acc[t][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[t], bh, acc[t][tn], 0, 0, 0);
         if constexpr (TERMS == 3) {
-          bf16x8 bl = *reinterpret_cast<const bf16x8*>(Bl + boff[tn] + kl);
-          if (bzero[tn]) bl = bf16x8{};
-          acc[tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[tn], 0, 0, 0);
-          acc[tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[tn], 0, 0, 0);
+          const bf16x8 bl = stage[buf][PLANES - 1][kq][16 * tn + r16];
+#pragma unroll
+          for (int t = 0; t < TM; ++t) {
+            acc[t][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[t], bl, acc[t][tn], 0, 0, 0);
+            acc[t][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[t], bh, acc[t][tn], 0, 0, 0);
+          }
         }
       }
+      if (more) {
+        store_b(buf ^ 1, breg);
+#pragma unroll
+        for (int t = 0; t < TM; ++t)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) a[t][e] = an[t][e];
+      }
+      __syncthreads();
     }
   }
   float* out = part + static_cast<int64_t>(blockIdx.y) * m * npad;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int orow = row_base + 4 * kq + j;
-    if (orow < m)
+  for (int t = 0; t < TM; ++t)
 #pragma unroll
-      for (int tn = 0; tn < NT; ++tn) out[orow * npad + 16 * tn + r16] = acc[tn][j];
-  }
+    for (int j = 0; j < 4; ++j) {
+      const int row = row_base + 16 * t + 4 * kq + j;
+      if (row < m)
+#pragma unroll
+        for (int tn = 0; tn < NT; ++tn) out[row * npad + 16 * tn + r16] = acc[t][tn][j];
+    }
 }
 
 template <int TERMS, bool VEC>
@@ -296,8 +417,8 @@ hipError_t bf16_dispatch(int nt, dim3 grid, hipStream_t st, int m, int n, int K,
                          int split_len, float* part, int npad) {
 #define GNM_BF_CASE(NT)                                                                        \
   case NT:                                                                                     \
-    hipLaunchKernelGGL((contract_bf16_kernel<TERMS, NT, VEC>), grid, dim3(256), 0, st, m, n, K, \
-                       R, ldr, r0, Bh, Bl, kpad, split_len, part, npad);                       \
+    hipLaunchKernelGGL((contract_bf16_kernel<TERMS, NT, kBf16RowTiles, VEC>), grid, dim3(256), 0, \
+                       st, m, n, K, R, ldr, r0, Bh, Bl, kpad, split_len, part, npad);          \
     break;
   switch (nt) {
     GNM_BF_CASE(1) GNM_BF_CASE(2) GNM_BF_CASE(3) GNM_BF_CASE(4) GNM_BF_CASE(5) GNM_BF_CASE(6)
@@ -310,6 +431,12 @@ hipError_t bf16_dispatch(int nt, dim3 grid, hipStream_t st, int m, int n, int K,
 }
 
 }  // namespace
+
+int contract_kw(size_t elem_size, int ncol) {
+  const int nt = (ncol + 15) / 16;
+  // the split epilogue parks 4 waves' tiles in LDS: stay within 64 KB
+  return static_cast<size_t>(4) * 16 * (16 * nt + 1) * elem_size <= 65536 ? 4 : 1;
+}
 
 hipError_t launch_contract(const ContractArgs<float>& a, int nsplit, hipStream_t st) {
   return contract_typed(a, nsplit, st);
@@ -328,7 +455,7 @@ hipError_t launch_split_bf16(int n, int K, int kpad, const float* W, int64_t ldw
 hipError_t launch_contract_bf16(int terms, int m, int n, int K, const float* R, int64_t ldr,
                                 const float* r0, const __bf16* Bh, const __bf16* Bl, int kpad,
                                 int nsplit, int split_len, float* part, int npad, hipStream_t st) {
-  dim3 grid((m + 63) / 64, nsplit);
+  dim3 grid((m + 64 * kBf16RowTiles - 1) / (64 * kBf16RowTiles), nsplit);
   const int nt = (n + 15) / 16;
   const bool vec = (ldr % 4 == 0) && (reinterpret_cast<uintptr_t>(R) % 16 == 0);
   if (terms == 3)

@@ -46,6 +46,12 @@ struct ContractArgs {
   int64_t split_stride;
   int ocols;
 };
+// Waves per block that share one 16-row output tile of launch_contract and
+// split its k-steps between them (the planner sizes k-splits with it).
+int contract_kw(size_t elem_size, int ncol);
+// launch_contract_bf16: 16-row MFMA tiles per wave (a block covers 64 times
+// as many rows) and the planner's target for its blocks per k-slice.
+constexpr int kBf16RowTiles = 1;
 hipError_t launch_contract(const ContractArgs<float>& a, int nsplit, hipStream_t st);
 hipError_t launch_contract(const ContractArgs<double>& a, int nsplit, hipStream_t st);
 
