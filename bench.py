@@ -266,6 +266,15 @@ def main():
         gaps = (costs - cstar) / abs(cstar)
         hit = np.nonzero(gaps <= 1e-3)[0]
         t_gn = evs[0].elapsed_time(evs[hit[0] + 1]) * 1e-3 if hit.size else None
+        # Method E: the same solver driven by the 2n-point sigma-point set
+        ge = GNMPPI(dp, w.x0, st, sampler="sigma_points", max_iters=st.iters)
+        torch.cuda.synchronize()
+        eevs = ge.solve(st.iters, events=True)
+        torch.cuda.synchronize()
+        ecosts, _, _ = ge.history(st.iters)
+        egaps = (ecosts - cstar) / abs(cstar)
+        ehit = np.nonzero(egaps <= 1e-3)[0]
+        t_e = eevs[0].elapsed_time(eevs[ehit[0] + 1]) * 1e-3 if ehit.size else None
         mp = PlainMPPI(dp, w.x0, st, seed=w.noise_seed + 200, max_iters=args.mppi_iters)
         e0 = torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -282,6 +291,9 @@ def main():
         mhit = np.nonzero(mgap[1:] <= 1e-3)[0]
         t_mp = e0.elapsed_time(mevs[mhit[0]]) * 1e-3 if mhit.size else None
         result["time_to_gap_s"] = {"gn_mppi": t_gn, "gn_mppi_iters": int(hit[0] + 1) if hit.size else None,
+                                   "gn_mppi_sigma_points": t_e,
+                                   "gn_mppi_sigma_points_iters": int(ehit[0] + 1) if ehit.size else None,
+                                   "gn_mppi_sigma_points_final_gap": float(egaps[-1]),
                                    "plain_mppi": t_mp,
                                    "plain_mppi_iters": int(mhit[0] + 1) if mhit.size else None,
                                    "gn_mppi_final_gap": float(gaps[-1]),
