@@ -212,6 +212,42 @@ int gnmppi_line_search(const gnmppi_problem *p, const void *x0, void *U,
                        const void *dU, const void *alpha, int32_t L, void *C,
                        double *info, void *stream);
 
+/* ---- learned warm start ----------------------------------------------------
+ *
+ * Not part of the paper's method: a perceptron proposes the initial control
+ * sequence U0(x0) from which Alg. 1 starts (GN-MPPI from zero remains the
+ * fallback).  Network: I -> H -> H -> O, GELU(z) = z Phi(z) after both hidden
+ * layers, linear output; loss L = sum (y - t)^2 / (2 B O) over a batch of B
+ * rows.
+ *
+ * params: bfloat16, flat, W1 (H x I), b1 (H), W2 (H x H), b2 (H), W3 (O x H),
+ * b3 (O), row-major (gnmppi_mlp_param_count elements).  Every matrix product
+ * rounds both operands to bfloat16 and accumulates in float32.  X (B x I),
+ * Y and T (B x O) are row-major float32.  `work` holds the activations of the
+ * last forward pass: gnmppi_mlp_workspace bytes, 256-byte aligned.
+ * 1 <= I, H, O <= 4096, 1 <= B <= 1 << 20; otherwise GNMPPI_EINVAL.  Device
+ * pointers, owned by the caller; nothing is allocated.                      */
+int64_t gnmppi_mlp_param_count(int32_t n_in, int32_t n_hidden, int32_t n_out);
+size_t gnmppi_mlp_workspace(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t batch);
+
+/* Y = net(X). */
+int gnmppi_mlp_forward(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t batch,
+                       const void *params, const float *X, float *Y, void *work,
+                       size_t work_bytes, void *stream);
+
+/* Forward pass, then loss (one float, may be NULL) and its gradient with
+ * respect to every parameter, in the parameter layout, float32. */
+int gnmppi_mlp_backward(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t batch,
+                        const void *params, const float *X, const float *T, float *loss,
+                        float *grad, void *work, size_t work_bytes, void *stream);
+
+/* One Adam step (Kingma and Ba) on `count` parameters: float32 master copy,
+ * moments m and v (float32, start at zero), step counted from 1; the bfloat16
+ * compute copy `params` is rewritten from the master. */
+int gnmppi_mlp_adam(int64_t count, float *master, void *params, const float *grad, float *m,
+                    float *v, double lr, double beta1, double beta2, double eps, int32_t step,
+                    void *stream);
+
 /* ---- misc ----------------------------------------------------------------- */
 const char *gnmppi_status_string(int32_t status);
 int32_t gnmppi_abi_version(void);

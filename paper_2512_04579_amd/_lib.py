@@ -63,6 +63,14 @@ SIGNATURES = {
                                   c_double, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
     "gnmppi_line_search": (c_int32, [PROBLEM_P, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
                                      c_void_p, c_void_p, c_void_p]),
+    "gnmppi_mlp_param_count": (c_int64, [c_int32, c_int32, c_int32]),
+    "gnmppi_mlp_workspace": (c_size_t, [c_int32, c_int32, c_int32, c_int32]),
+    "gnmppi_mlp_forward": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                     c_void_p, c_size_t, c_void_p]),
+    "gnmppi_mlp_backward": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                      c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "gnmppi_mlp_adam": (c_int32, [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double,
+                                  c_double, c_double, c_double, c_int32, c_void_p]),
     "gnmppi_status_string": (ctypes.c_char_p, [c_int32]),
     "gnmppi_abi_version": (c_int32, []),
 }
@@ -201,6 +209,39 @@ def gnmppi_line_search(problem, x0, U, dU, alpha, C=None, info=None, stream=None
     _check("gnmppi_line_search", load().gnmppi_line_search(
         ctypes.byref(problem.c), _ptr(x0), _ptr(U), _ptr(dU), _ptr(alpha), alpha.numel(), _ptr(C),
         _ptr(info), _stream(stream)))
+
+
+def gnmppi_mlp_param_count(n_in: int, n_hidden: int, n_out: int) -> int:
+    return int(load().gnmppi_mlp_param_count(n_in, n_hidden, n_out))
+
+
+def gnmppi_mlp_workspace(n_in: int, n_hidden: int, n_out: int, batch: int) -> int:
+    return int(load().gnmppi_mlp_workspace(n_in, n_hidden, n_out, batch))
+
+
+def _nbytes(t):
+    return t.numel() * t.element_size()
+
+
+def gnmppi_mlp_forward(dims, params, X, Y, work, stream=None):
+    """dims = (n_in, n_hidden, n_out); params bfloat16; X (B, I), Y (B, O) float32."""
+    I, H, O = dims
+    _check("gnmppi_mlp_forward", load().gnmppi_mlp_forward(
+        I, H, O, X.shape[0], _ptr(params), _ptr(X), _ptr(Y), _ptr(work), _nbytes(work), _stream(stream)))
+
+
+def gnmppi_mlp_backward(dims, params, X, T, loss, grad, work, stream=None):
+    I, H, O = dims
+    _check("gnmppi_mlp_backward", load().gnmppi_mlp_backward(
+        I, H, O, X.shape[0], _ptr(params), _ptr(X), _ptr(T), _ptr(loss), _ptr(grad), _ptr(work),
+        _nbytes(work), _stream(stream)))
+
+
+def gnmppi_mlp_adam(master, params, grad, m, v, lr: float, step: int, beta1: float = 0.9,
+                    beta2: float = 0.999, eps: float = 1e-8, stream=None):
+    _check("gnmppi_mlp_adam", load().gnmppi_mlp_adam(
+        master.numel(), _ptr(master), _ptr(params), _ptr(grad), _ptr(m), _ptr(v), float(lr),
+        float(beta1), float(beta2), float(eps), int(step), _stream(stream)))
 
 
 def gnmppi_abi_version() -> int:

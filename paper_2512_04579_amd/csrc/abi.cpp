@@ -153,6 +153,52 @@ int gnmppi_line_search(const gnmppi_problem* p, const void* x0, void* U, const v
   return status_of(gnm::launch_line_search(*p, x0, U, dU, alpha, L, C, info, as_stream(stream)));
 }
 
+int64_t gnmppi_mlp_param_count(int32_t n_in, int32_t n_hidden, int32_t n_out) {
+  if (n_in < 1 || n_hidden < 1 || n_out < 1 || n_in > 4096 || n_hidden > 4096 || n_out > 4096)
+    return 0;
+  return gnm::mlp_param_count(n_in, n_hidden, n_out);
+}
+
+size_t gnmppi_mlp_workspace(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t batch) {
+  if (gnmppi_mlp_param_count(n_in, n_hidden, n_out) == 0 || batch < 1 || batch > (1 << 20)) return 0;
+  return gnm::mlp_workspace_bytes(n_hidden, n_out, batch);
+}
+
+int gnmppi_mlp_forward(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t batch,
+                       const void* params, const float* X, float* Y, void* work, size_t work_bytes,
+                       void* stream) {
+  const size_t need = gnmppi_mlp_workspace(n_in, n_hidden, n_out, batch);
+  if (need == 0 || params == nullptr || X == nullptr || Y == nullptr || work == nullptr ||
+      !aligned256(work))
+    return GNMPPI_EINVAL;
+  if (work_bytes < need) return GNMPPI_ENOSPACE;
+  return status_of(gnm::launch_mlp_forward(n_in, n_hidden, n_out, batch, params, X, Y, work,
+                                           as_stream(stream)));
+}
+
+int gnmppi_mlp_backward(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t batch,
+                        const void* params, const float* X, const float* T, float* loss,
+                        float* grad, void* work, size_t work_bytes, void* stream) {
+  const size_t need = gnmppi_mlp_workspace(n_in, n_hidden, n_out, batch);
+  if (need == 0 || params == nullptr || X == nullptr || T == nullptr || grad == nullptr ||
+      work == nullptr || !aligned256(work))
+    return GNMPPI_EINVAL;
+  if (work_bytes < need) return GNMPPI_ENOSPACE;
+  return status_of(gnm::launch_mlp_backward(n_in, n_hidden, n_out, batch, params, X, T, loss, grad,
+                                            work, as_stream(stream)));
+}
+
+int gnmppi_mlp_adam(int64_t count, float* master, void* params, const float* grad, float* m,
+                    float* v, double lr, double beta1, double beta2, double eps, int32_t step,
+                    void* stream) {
+  if (count < 1 || master == nullptr || params == nullptr || grad == nullptr || m == nullptr ||
+      v == nullptr || step < 1 || !(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) ||
+      !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0) || count > (int64_t{1} << 40))
+    return GNMPPI_EINVAL;
+  return status_of(gnm::launch_mlp_adam(count, master, params, grad, m, v, lr, beta1, beta2, eps,
+                                        step, as_stream(stream)));
+}
+
 const char* gnmppi_status_string(int32_t status) {
   switch (status) {
     case GNMPPI_OK: return "ok";

@@ -102,5 +102,16 @@ hipError_t launch_ggn(int dtype, int m, int n, const void* J, int64_t ldj, const
                       int64_t inc_r0, double lm_lambda, void* dU, void* work,
                       int32_t* status, hipStream_t st);
 
+// Warm-start perceptron I -> H -> H -> O (mlp.hip).
+int64_t mlp_param_count(int I, int H, int O);
+size_t mlp_workspace_bytes(int H, int O, int batch);
+hipError_t launch_mlp_forward(int I, int H, int O, int batch, const void* params, const float* X,
+                              float* Y, void* work, hipStream_t st);
+hipError_t launch_mlp_backward(int I, int H, int O, int batch, const void* params, const float* X,
+                               const float* T, float* loss, float* grad, void* work,
+                               hipStream_t st);
+hipError_t launch_mlp_adam(int64_t count, float* master, void* params, const float* grad, float* m,
+                           float* v, double lr, double beta1, double beta2, double eps, int step,
+                           hipStream_t st);
 
 }  // namespace gnm

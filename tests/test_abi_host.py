@@ -146,3 +146,19 @@ def test_status_strings_and_version():
     assert _lib.status_string(_lib.ENOTPD) == "normal matrix not positive definite"
     assert _lib.status_string(123) == "unknown status"
     assert _lib.gnmppi_abi_version() == 1
+
+
+def test_mlp_entry_points_reject_bad_arguments():
+    lib = _lib.load()
+    assert lib.gnmppi_mlp_param_count(64, 256, 100) == 256 * 64 + 256 + 256 * 256 + 256 + 100 * 256 + 100
+    assert lib.gnmppi_mlp_param_count(0, 256, 100) == 0
+    ws = lib.gnmppi_mlp_workspace(64, 256, 100, 1024)
+    assert ws == (6 * 1024 * 256 + 2 * 1024 * 100) * 4
+    assert lib.gnmppi_mlp_workspace(64, 256, 100, 0) == 0
+    assert lib.gnmppi_mlp_forward(64, 256, 100, 1024, 0x100, 0x200, 0x300, 0x1000, ws - 4, None) == _lib.ENOSPACE
+    assert lib.gnmppi_mlp_forward(64, 256, 100, 1024, 0x100, 0x200, 0x300, 0x1008, ws, None) == _lib.EINVAL
+    assert lib.gnmppi_mlp_forward(64, 5000, 100, 1024, 0x100, 0x200, 0x300, 0x1000, ws, None) == _lib.EINVAL
+    assert lib.gnmppi_mlp_backward(64, 256, 100, 1024, 0x100, 0x200, None, None, 0x400, 0x1000, ws,
+                                   None) == _lib.EINVAL
+    assert lib.gnmppi_mlp_adam(10, 0x10, 0x20, 0x30, 0x40, 0x50, 1e-3, 0.9, 0.999, 1e-8, 0, None) == _lib.EINVAL
+    assert lib.gnmppi_mlp_adam(10, 0x10, 0x20, 0x30, 0x40, 0x50, 1e-3, 1.0, 0.999, 1e-8, 1, None) == _lib.EINVAL

@@ -16,6 +16,8 @@ Workloads (paper: direct single-shooting OCP of Sec. 2, Eqs. (1)-(4)):
   nonlinear pendulum of Problem V, whose model is given only by citation.
 * ``c4`` -- the same chain at N=66, K=8192 (precision-split workload).
 * ``c3`` -- batches of independent chain instances of uneven size.
+* warm-start data -- initial states of the chain instance drawn like its x0
+  (``chain_initial_states``), solved by GN-MPPI to give (x0, U*) pairs.
 """
 from __future__ import annotations
 
@@ -202,6 +204,23 @@ def gaussian_perturbations(n: int, K: int, sigma: float, seed: int,
         Z = rng.standard_normal((n, K // 2))
         return sigma * np.concatenate([Z, -Z], axis=1)
     return sigma * rng.standard_normal((n, K))
+
+
+def chain_initial_states(count: int, seed: int, n_masses: int = 16) -> np.ndarray:
+    """Initial states drawn like the chain instance's x0 (rest pose for
+    e0 ~ U[-1,1]^2, U[-0.1,0.1] jitter on the free masses' positions and
+    velocities, end mass at rest): the inputs of the warm-start data set,
+    ``count`` x 4 M."""
+    rng = np.random.default_rng(seed)
+    M = n_masses
+    free = 2 * (M - 1)
+    out = np.empty((count, 4 * M))
+    for i in range(count):
+        x0 = chain_rest_pose(M, rng.uniform(-1.0, 1.0, 2))
+        x0[:free] += rng.uniform(-0.1, 0.1, free)
+        x0[2 * M:2 * M + free] += rng.uniform(-0.1, 0.1, free)
+        out[i] = x0
+    return out
 
 
 def random_controls(n: int, scale: float, seed: int) -> np.ndarray:
