@@ -9,8 +9,8 @@ backpropagation and Adam run in the library's kernels (gnmppi_mlp_*);
 PyTorch only holds the tensors.
 
 The zero start stays both the fallback and the judge: ``start_controls``
-rolls out the proposal and U = 0 and keeps whichever costs less, and the
-gain is measured against GN-MPPI from zero.
+rolls out the proposal and U = 0 in one launch and keeps whichever costs
+less, and the gain is measured against GN-MPPI from zero.
 
 Command line (one GPU):
     python -m paper_2512_04579_amd.warmstart --pairs 100000 --epochs 40 \
@@ -61,6 +61,7 @@ class WarmStartNet:
         self.y_mean, self.y_std = np.zeros(O), np.ones(O)
         self._work = {}
         self._folded = None
+        self._alpha = {}
 
     # -- helpers -------------------------------------------------------------
     def _workspace(self, batch: int) -> torch.Tensor:
@@ -164,19 +165,24 @@ class WarmStartNet:
         return net
 
 
-def start_controls(net: WarmStartNet, dprob: DeviceProblem, x0: torch.Tensor, U: torch.Tensor):
+def start_controls(net: WarmStartNet, dprob: DeviceProblem, x0: torch.Tensor, U: torch.Tensor,
+                   info: torch.Tensor | None = None) -> torch.Tensor:
     """Writes the start U of GN-MPPI for initial state x0 into ``U``: the
-    network's proposal, or zero if the proposal's nominal rollout costs more
-    (or is not finite).  Returns (chosen, C(proposal), C(0))."""
+    network's proposal, or zero if the proposal's rollout costs more (or is
+    not finite).  Done on the device without a host round trip: the line
+    search of Eq. (15) from U = 0 along the proposal with step lengths
+    {1, 0} evaluates both candidates in one launch and applies the cheaper
+    (ties go to the proposal).  Returns ``info`` = {alpha*, C*, j*}
+    (alpha* = 1: the network's start was taken)."""
     prop = net.predict(x0.reshape(1, -1).to(torch.float32))[0]
-    zero = torch.zeros_like(U)
-    costs = torch.empty(2, dtype=U.dtype, device=U.device)
-    _lib.gnmppi_rollout(dprob, x0, prop.to(U.dtype), None, 0, None, None, None, costs[0:1])
-    _lib.gnmppi_rollout(dprob, x0, zero, None, 0, None, None, None, costs[1:2])
-    c_prop, c_zero = (float(c) for c in costs.cpu())
-    use = np.isfinite(c_prop) and c_prop < c_zero
-    U.copy_(prop if use else zero)
-    return ("network" if use else "zero"), c_prop, c_zero
+    U.zero_()
+    key = (U.dtype, U.device)
+    if key not in net._alpha:  # kept on the device: no host copy per call
+        net._alpha[key] = torch.tensor([1.0, 0.0], dtype=U.dtype, device=U.device)
+    if info is None:
+        info = torch.empty(3, dtype=torch.float64, device=U.device)
+    _lib.gnmppi_line_search(dprob, x0, U, prop.to(U.dtype), net._alpha[key], None, info)
+    return info
 
 
 def solve_pairs(workload, X0: np.ndarray, iters: int, seed: int | None = None, log=None):

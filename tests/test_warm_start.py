@@ -59,8 +59,8 @@ def test_warm_start_beats_the_zero_start():
     for x0 in X_test:
         x0d = dp.tensor(x0)
         U = torch.zeros(p.n, dtype=torch.float32, device=dp.device)
-        which, _, _ = start_controls(net, dp, x0d, U)
-        chosen.append(which)
+        info = start_controls(net, dp, x0d, U)
+        chosen.append("network" if info[0].item() == 1.0 else "zero")
         warm_starts.append(U.clone())
         zero_starts.append(torch.zeros_like(U))
     g_zero = _gaps(w, dp, solver, graph, X_test, zero_starts, cstar, iters)
@@ -75,3 +75,20 @@ def test_warm_start_beats_the_zero_start():
     assert med_warm[0] < 0.01 * med_zero[0]
     # ... and one GN-MPPI iteration from it lands closer than one from zero
     assert med_warm[1] < med_zero[1]
+
+
+def test_start_controls_falls_back_to_zero():
+    """A proposal that costs more than U = 0 is not taken."""
+    w = wl.c2()
+    p = w.problem
+    dp = DeviceProblem(p, "f32")
+    net = WarmStartNet(p.nx, p.n, seed=0)
+    with torch.no_grad():
+        net.master.mul_(0.0)
+        net.master[-p.n:] = 50.0   # b3: a huge constant control sequence
+    net.params = net.master.to(torch.bfloat16)
+    net._folded = None
+    U = torch.full((p.n,), 7.0, dtype=torch.float32, device=dp.device)
+    info = start_controls(net, dp, dp.tensor(w.x0), U)
+    assert info[0].item() == 0.0 and info[2].item() == 1
+    assert torch.count_nonzero(U).item() == 0
