@@ -212,6 +212,71 @@ int gnmppi_line_search(const gnmppi_problem *p, const void *x0, void *U,
                        const void *dU, const void *alpha, int32_t L, void *C,
                        double *info, void *stream);
 
+/* ---- batched iterations ----------------------------------------------------
+ *
+ * Many independent chain MPC instances of uneven size solved together: one
+ * GN-MPPI iteration (Alg. 1: sample, rollout, Jacobian reconstruction of
+ * Eq. (10) in the LS form with the BF16x3 sample contraction, GGN step of
+ * Eq. (13) in FP64, line search of Eqs. (14)-(15)) for every instance is
+ * enqueued by one call, as a few persistent launches per step (one per
+ * shape class), so that the whole iteration can be captured in a HIP graph.
+ *
+ * `shared`: the chain model parameters common to all instances (model =
+ * GNMPPI_MODEL_CHAIN, dtype = GNMPPI_F32, dt, k_lin, k_cub, mass; the size
+ * fields and q / r / x_ref are ignored).  Instance b: 3 <= n_masses <= 16,
+ * 1 <= N <= 80, K even with K / 2 >= 2 N (antithetic pairs must span the
+ * decisions), K <= 65536; device float32 x0 (4M), q (4M), r (2), x_ref (4M)
+ * and U (2N, the iterate, updated in place); status (2 int32: Jacobian rank,
+ * GGN positive definiteness, as the single-instance calls report them) and
+ * info (3 doubles: alpha*, C*, j* of the last line search).  Instance b
+ * draws its perturbations from Philox key seed + b and stream id = the
+ * iteration index, exactly as gnmppi_sample with that seed would.
+ *
+ * The workspace (gnmppi_batch_workspace bytes, 256-byte aligned, owned by
+ * the caller) holds the per-instance W, R, S, J and solve buffers and the
+ * work tables; gnmppi_batch_prepare fills the tables (synchronous copies,
+ * call it once, outside graph capture).  gnmppi_batch_iteration only
+ * enqueues kernels on `stream` and must be given the same instances,
+ * settings and tuning as the prepare call.  The tuning fields only change
+ * launch shapes and k-slices (0 = default); any value gives a correct
+ * result.  Errors: GNMPPI_EINVAL for a rejected argument, GNMPPI_ENOSPACE
+ * for a short workspace. */
+typedef struct {
+  int32_t n_masses, N, K, reserved;
+  const void *x0, *q, *r, *x_ref;
+  void *U;
+  int32_t *status;
+  double *info;
+} gnmppi_batch_instance;
+
+typedef struct {
+  uint64_t seed;     /* instance b uses Philox key seed + b */
+  double gamma;      /* line-search ratio, 0 < gamma < 1 */
+  int32_t n_alpha;   /* line-search candidates gamma^j, 1 <= n_alpha <= 64 */
+  int32_t reserved;
+  double lm_lambda;  /* lambda added to the diagonal of J^T J (>= 0) */
+} gnmppi_batch_settings;
+
+typedef struct {
+  int32_t rollout_blocks_per_cu;   /* persistent grid of the rollout */
+  int32_t contract_blocks_per_cu;  /* persistent grid of S = dR W^T */
+  int32_t contract_ksplit;         /* k-slices of S per instance */
+  int32_t small_blocks_per_cu;     /* persistent grid of the other steps */
+} gnmppi_batch_tuning;
+
+size_t gnmppi_batch_workspace(const gnmppi_problem *shared, int32_t count,
+                              const gnmppi_batch_instance *inst,
+                              const gnmppi_batch_settings *settings,
+                              const gnmppi_batch_tuning *tuning);
+int gnmppi_batch_prepare(const gnmppi_problem *shared, int32_t count,
+                         const gnmppi_batch_instance *inst, const gnmppi_batch_settings *settings,
+                         const gnmppi_batch_tuning *tuning, void *work, size_t work_bytes);
+int gnmppi_batch_iteration(const gnmppi_problem *shared, int32_t count,
+                           const gnmppi_batch_instance *inst,
+                           const gnmppi_batch_settings *settings,
+                           const gnmppi_batch_tuning *tuning, void *work, size_t work_bytes,
+                           int32_t it, double sigma, void *stream);
+
 /* ---- learned warm start ----------------------------------------------------
  *
  * Not part of the paper's method: a perceptron proposes the initial control

@@ -39,7 +39,30 @@ class GnmppiProblem(ctypes.Structure):
     ]
 
 
+class GnmppiBatchInstance(ctypes.Structure):
+    """Mirror of ``gnmppi_batch_instance``."""
+
+    _fields_ = [
+        ("n_masses", c_int32), ("N", c_int32), ("K", c_int32), ("reserved", c_int32),
+        ("x0", c_void_p), ("q", c_void_p), ("r", c_void_p), ("x_ref", c_void_p),
+        ("U", c_void_p), ("status", c_void_p), ("info", c_void_p),
+    ]
+
+
+class GnmppiBatchSettings(ctypes.Structure):
+    _fields_ = [("seed", c_uint64), ("gamma", c_double), ("n_alpha", c_int32),
+                ("reserved", c_int32), ("lm_lambda", c_double)]
+
+
+class GnmppiBatchTuning(ctypes.Structure):
+    _fields_ = [("rollout_blocks_per_cu", c_int32), ("contract_blocks_per_cu", c_int32),
+                ("contract_ksplit", c_int32), ("small_blocks_per_cu", c_int32)]
+
+
 PROBLEM_P = ctypes.POINTER(GnmppiProblem)
+BATCH_P = ctypes.POINTER(GnmppiBatchInstance)
+BSET_P = ctypes.POINTER(GnmppiBatchSettings)
+BTUNE_P = ctypes.POINTER(GnmppiBatchTuning)
 I32_P = ctypes.POINTER(c_int32)
 F64_P = ctypes.POINTER(c_double)
 
@@ -63,6 +86,10 @@ SIGNATURES = {
                                   c_double, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
     "gnmppi_line_search": (c_int32, [PROBLEM_P, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
                                      c_void_p, c_void_p, c_void_p]),
+    "gnmppi_batch_workspace": (c_size_t, [PROBLEM_P, c_int32, BATCH_P, BSET_P, BTUNE_P]),
+    "gnmppi_batch_prepare": (c_int32, [PROBLEM_P, c_int32, BATCH_P, BSET_P, BTUNE_P, c_void_p, c_size_t]),
+    "gnmppi_batch_iteration": (c_int32, [PROBLEM_P, c_int32, BATCH_P, BSET_P, BTUNE_P, c_void_p,
+                                         c_size_t, c_int32, c_double, c_void_p]),
     "gnmppi_mlp_param_count": (c_int64, [c_int32, c_int32, c_int32]),
     "gnmppi_mlp_workspace": (c_size_t, [c_int32, c_int32, c_int32, c_int32]),
     "gnmppi_mlp_forward": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
@@ -209,6 +236,24 @@ def gnmppi_line_search(problem, x0, U, dU, alpha, C=None, info=None, stream=None
     _check("gnmppi_line_search", load().gnmppi_line_search(
         ctypes.byref(problem.c), _ptr(x0), _ptr(U), _ptr(dU), _ptr(alpha), alpha.numel(), _ptr(C),
         _ptr(info), _stream(stream)))
+
+
+def gnmppi_batch_workspace(shared, count, inst, settings, tuning) -> int:
+    return int(load().gnmppi_batch_workspace(ctypes.byref(shared), int(count), inst,
+                                             ctypes.byref(settings), ctypes.byref(tuning)))
+
+
+def gnmppi_batch_prepare(shared, count, inst, settings, tuning, work):
+    _check("gnmppi_batch_prepare", load().gnmppi_batch_prepare(
+        ctypes.byref(shared), int(count), inst, ctypes.byref(settings), ctypes.byref(tuning),
+        _ptr(work), _nbytes(work)))
+
+
+def gnmppi_batch_iteration(shared, count, inst, settings, tuning, work, it: int, sigma: float,
+                           stream=None):
+    _check("gnmppi_batch_iteration", load().gnmppi_batch_iteration(
+        ctypes.byref(shared), int(count), inst, ctypes.byref(settings), ctypes.byref(tuning),
+        _ptr(work), _nbytes(work), int(it), float(sigma), _stream(stream)))
 
 
 def gnmppi_mlp_param_count(n_in: int, n_hidden: int, n_out: int) -> int:

@@ -19,7 +19,8 @@ BUILD_DIR = os.path.join(HERE, "_build")
 LIB_PATH = os.path.join(HERE, "libgnmppi.so")
 ARCH = "gfx950"
 
-SOURCES = ["abi.cpp", "sample.hip", "rollout.hip", "mppi.hip", "gemm.hip", "dense.hip", "mlp.hip"]
+SOURCES = ["abi.cpp", "batch.cpp", "sample.hip", "rollout.hip", "mppi.hip", "gemm.hip", "dense.hip",
+           "mlp.hip"]
 
 # Packed FP32 VALU ops are switched off for every HIP translation unit.
 HIPCC_FLAGS = [

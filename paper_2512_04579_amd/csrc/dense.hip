@@ -23,6 +23,7 @@
 //  * gram_kernel<NT> -- the lower tiles of [J r0]^T [J r0] over a chunk of
 //      rows with the 16x16x4 f64 MFMA (products of float inputs are exact in
 //      double); one partial sum per chunk.
+#include "batch.hpp"
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -41,11 +42,11 @@ using f64x4 = double __attribute__((ext_vector_type(4)));
 // reading only entries j <= i; diag_shift is added to the first npiv diagonal
 // entries.  grid.x = P (one row each), block = 256 >= P.
 template <typename TP>
-__global__ void __launch_bounds__(256) reduce_sym_kernel(const TP* __restrict__ part, int nsplit,
-                                                         int64_t split_stride, int row0, int ldp,
-                                                         int P, int npiv, double diag_shift,
-                                                         double* __restrict__ out) {
-  const int i = blockIdx.x, j = threadIdx.x;
+__device__ __forceinline__ void reduce_sym_row(const TP* __restrict__ part, int nsplit,
+                                               int64_t split_stride, int row0, int ldp, int P,
+                                               int npiv, double diag_shift,
+                                               double* __restrict__ out, int i) {
+  const int j = threadIdx.x;
   if (j > i) return;
   const TP* src = part + static_cast<int64_t>(row0 + i) * ldp + j;
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
@@ -61,6 +62,32 @@ __global__ void __launch_bounds__(256) reduce_sym_kernel(const TP* __restrict__ 
   if (i == j && i < npiv) s += diag_shift;
   out[static_cast<int64_t>(i) * P + j] = s;
   out[static_cast<int64_t>(j) * P + i] = s;
+}
+
+template <typename TP>
+__global__ void __launch_bounds__(256) reduce_sym_kernel(const TP* __restrict__ part, int nsplit,
+                                                         int64_t split_stride, int row0, int ldp,
+                                                         int P, int npiv, double diag_shift,
+                                                         double* __restrict__ out) {
+  reduce_sym_row<TP>(part, nsplit, split_stride, row0, ldp, P, npiv, diag_shift, out, blockIdx.x);
+}
+
+// Batched: MODE 0 reduces the G = W W^T partials into Gsum (P = n), MODE 1
+// the [J r0]^T [J r0] partials into Hsum (P = n + 1, lambda on the first n
+// diagonal entries).  tile = row i.
+template <int MODE>
+__global__ void __launch_bounds__(256) batch_reduce_sym_kernel(const BatchInst* __restrict__ inst,
+                                                               BatchLaunch L, double lm_lambda) {
+  for (int w = blockIdx.x; w < L.count; w += gridDim.x) {
+    const BatchItem it = L.items[w];
+    const BatchInst& b = inst[it.inst];
+    if constexpr (MODE == 0)
+      reduce_sym_row<float>(b.gpart, b.gsplit, static_cast<int64_t>(b.n) * b.npad, 0, b.npad, b.n,
+                            b.n, 0.0, b.Gsum, it.tile);
+    else
+      reduce_sym_row<double>(b.hpart, b.hsplit, static_cast<int64_t>(b.n + 1) * (b.n + 1), 0,
+                             b.n + 1, b.n + 1, b.n, lm_lambda, b.Hsum, it.tile);
+  }
 }
 
 // ---- blocked register-resident symmetric sweep ------------------------------
@@ -229,7 +256,7 @@ __device__ __forceinline__ bool sweep_blocks(double (&A)[R][R], double* __restri
 }
 
 template <int R, typename TO>
-__global__ void __launch_bounds__(kSweepTD * kSweepTD) sweep_kernel(
+__device__ __forceinline__ void sweep_matrix(
     const double* __restrict__ M, int P, int npiv, int mode, TO* __restrict__ inv_out, int64_t ldo,
     TO* __restrict__ dir_out, int32_t* status, int fail_code) {
   constexpr int TD = kSweepTD, LD = kSweepLd;
@@ -295,6 +322,30 @@ __global__ void __launch_bounds__(kSweepTD * kSweepTD) sweep_kernel(
   if (threadIdx.x == 0 && status) *status = ok ? GNMPPI_OK : fail_code;
 }
 
+template <int R, typename TO>
+__global__ void __launch_bounds__(kSweepTD * kSweepTD) sweep_kernel(
+    const double* __restrict__ M, int P, int npiv, int mode, TO* __restrict__ inv_out, int64_t ldo,
+    TO* __restrict__ dir_out, int32_t* status, int fail_code) {
+  sweep_matrix<R, TO>(M, P, npiv, mode, inv_out, ldo, dir_out, status, fail_code);
+}
+
+// Batched: MODE 0 inverts Gsum into Ginv (status word 0), MODE 1 solves the
+// GGN direction from Hsum into dU (status word 1).  One item per instance.
+template <int R, int MODE>
+__global__ void __launch_bounds__(kSweepTD * kSweepTD) batch_sweep_kernel(
+    const BatchInst* __restrict__ inst, BatchLaunch L) {
+  for (int w = blockIdx.x; w < L.count; w += gridDim.x) {
+    const BatchInst& b = inst[L.items[w].inst];
+    if constexpr (MODE == 0)
+      sweep_matrix<R, float>(b.Gsum, b.n, b.n, kSweepInverse, b.Ginv, b.npad, nullptr, b.status,
+                             GNMPPI_ERANK);
+    else
+      sweep_matrix<R, float>(b.Hsum, b.n + 1, b.n, kSweepDirection, nullptr, 0, b.dU,
+                             b.status + 1, GNMPPI_ENOTPD);
+    __syncthreads();
+  }
+}
+
 // One workgroup of 16 x 16 threads; R = ceil(P / 16) <= 13 for P <= 208.
 template <typename TO>
 hipError_t launch_sweep(int P, int npiv, int mode, const double* M, TO* inv_out, int64_t ldo,
@@ -321,13 +372,13 @@ hipError_t launch_sweep(int P, int npiv, int mode, const double* M, TO* inv_out,
 // out[i, c] = scale * sum_sp part[sp][i, c] for i < m, c < n: 4 rows x 64
 // columns per block, one element per thread, all partial loads in flight.
 template <typename T>
-__global__ void __launch_bounds__(256) reduce_rows_kernel(const T* __restrict__ part, int nsplit,
-                                                          int64_t split_stride, int ldp, int m,
-                                                          int n, double scale, T* __restrict__ out,
-                                                          int64_t ldo, int32_t* status) {
-  if (status && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *status = GNMPPI_OK;
-  const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
-  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+__device__ __forceinline__ void reduce_rows_block(const T* __restrict__ part, int nsplit,
+                                                  int64_t split_stride, int ldp, int m, int n,
+                                                  double scale, T* __restrict__ out, int64_t ldo,
+                                                  int32_t* status, int bx, int by) {
+  if (status && bx == 0 && by == 0 && threadIdx.x == 0) *status = GNMPPI_OK;
+  const int i = by * 4 + (threadIdx.x >> 6);
+  const int c = bx * 64 + (threadIdx.x & 63);
   if (i >= m || c >= n) return;
   const T* src = part + static_cast<int64_t>(i) * ldp + c;
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
@@ -342,20 +393,40 @@ __global__ void __launch_bounds__(256) reduce_rows_kernel(const T* __restrict__ 
   out[i * ldo + c] = static_cast<T>(((s0 + s1) + (s2 + s3)) * scale);
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) reduce_rows_kernel(const T* __restrict__ part, int nsplit,
+                                                          int64_t split_stride, int ldp, int m,
+                                                          int n, double scale, T* __restrict__ out,
+                                                          int64_t ldo, int32_t* status) {
+  reduce_rows_block<T>(part, nsplit, split_stride, ldp, m, n, scale, out, ldo, status, blockIdx.x,
+                       blockIdx.y);
+}
+
+// Batched S = sum of the k-slices; tile = row group * ceil(n / 64) + column group.
+__global__ void __launch_bounds__(256) batch_reduce_rows_kernel(const BatchInst* __restrict__ inst,
+                                                                BatchLaunch L) {
+  for (int w = blockIdx.x; w < L.count; w += gridDim.x) {
+    const BatchItem it = L.items[w];
+    const BatchInst& b = inst[it.inst];
+    const int xb = (b.n + 63) / 64;
+    reduce_rows_block<float>(b.part, b.nsplit, static_cast<int64_t>(b.m) * b.npad, b.npad, b.m,
+                             b.n, 1.0, b.S, b.npad, nullptr, it.tile % xb, it.tile / xb);
+  }
+}
+
 // ---- [J r0]^T [J r0] with the f64 MFMA ------------------------------------------
 
 // f64 16x16x4 MFMA: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
 // accumulator element j of lane l is D[4 j + l / 16][l % 16].
 template <typename T, int NT>
-__global__ void __launch_bounds__(256) gram_kernel(int m, int n, const T* __restrict__ J,
-                                                   int64_t ldj, const T* __restrict__ r0,
-                                                   int64_t inc, int chunk, int P,
-                                                   double* __restrict__ part) {
+__device__ __forceinline__ void gram_chunk(int m, int n, const T* __restrict__ J, int64_t ldj,
+                                           const T* __restrict__ r0, int64_t inc, int chunk, int P,
+                                           double* __restrict__ part, int bx) {
   constexpr int NPAIR = NT * (NT + 1) / 2;
   constexpr int NACC = (NPAIR + 3) / 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
-  const int ibeg = blockIdx.x * chunk, iend = min(m, ibeg + chunk);
+  const int ibeg = bx * chunk, iend = min(m, ibeg + chunk);
   f64x4 acc[NACC];
 #pragma unroll
   for (int q = 0; q < NACC; ++q) acc[q] = f64x4{0, 0, 0, 0};
@@ -383,7 +454,7 @@ __global__ void __launch_bounds__(256) gram_kernel(int m, int n, const T* __rest
         if ((q & 3) == wave)
           acc[q >> 2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[ta], x[tb], acc[q >> 2], 0, 0, 0);
   }
-  double* out = part + static_cast<int64_t>(blockIdx.x) * P * P;
+  double* out = part + static_cast<int64_t>(bx) * P * P;
   int q = 0;
 #pragma unroll
   for (int ta = 0; ta < NT; ++ta)
@@ -396,6 +467,25 @@ __global__ void __launch_bounds__(256) gram_kernel(int m, int n, const T* __rest
           if (a < P && b < P) out[static_cast<int64_t>(a) * P + b] = acc[q >> 2][j];
         }
       }
+}
+
+template <typename T, int NT>
+__global__ void __launch_bounds__(256) gram_kernel(int m, int n, const T* __restrict__ J,
+                                                   int64_t ldj, const T* __restrict__ r0,
+                                                   int64_t inc, int chunk, int P,
+                                                   double* __restrict__ part) {
+  gram_chunk<T, NT>(m, n, J, ldj, r0, inc, chunk, P, part, blockIdx.x);
+}
+
+// Batched [J r0]^T [J r0] partials; tile = row chunk.
+template <int NT>
+__global__ void __launch_bounds__(256) batch_gram_kernel(const BatchInst* __restrict__ inst,
+                                                         BatchLaunch L) {
+  for (int w = blockIdx.x; w < L.count; w += gridDim.x) {
+    const BatchItem it = L.items[w];
+    const BatchInst& b = inst[it.inst];
+    gram_chunk<float, NT>(b.m, b.n, b.J, b.n, b.r0, 1, b.hchunk, b.n + 1, b.hpart, it.tile);
+  }
 }
 
 template <typename T>
@@ -419,8 +509,6 @@ hipError_t launch_gram(int nt, int nblocks, hipStream_t st, int m, int n, const 
 
 }  // namespace
 
-// k-split plan: enough slices that ~1.5k waves (16 rows each) cover the
-// machine, at least two MFMA k-steps per slice.
 // k-split of a contraction over `rows` output rows: every wave owns a 16-row
 // tile and one of the kw step sequences of a slice; aim at ~4k waves (4 per
 // SIMD) with at least two steps per wave and steps spread evenly.
@@ -642,6 +730,64 @@ hipError_t launch_ggn(int dtype, int m, int n, const void* J, int64_t ldj, const
                                status, GNMPPI_ENOTPD, st);
   return launch_sweep<double>(g.P, n, kSweepDirection, Hsum, nullptr, 0, static_cast<double*>(dU),
                               status, GNMPPI_ENOTPD, st);
+}
+
+// ---- batched launchers ------------------------------------------------------
+
+hipError_t launch_batch_reduce_sym(int mode, const BatchInst* inst, const BatchLaunch& L,
+                                   double lm_lambda, hipStream_t st) {
+  if (L.count == 0) return hipSuccess;
+  if (mode == 0)
+    hipLaunchKernelGGL(batch_reduce_sym_kernel<0>, dim3(L.blocks), dim3(256), 0, st, inst, L,
+                       lm_lambda);
+  else
+    hipLaunchKernelGGL(batch_reduce_sym_kernel<1>, dim3(L.blocks), dim3(256), 0, st, inst, L,
+                       lm_lambda);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_sweep(int mode, int R, const BatchInst* inst, const BatchLaunch& L,
+                              hipStream_t st) {
+  if (L.count == 0) return hipSuccess;
+#define GNM_BS_CASE(RR)                                                                         \
+  case RR:                                                                                      \
+    if (mode == 0)                                                                              \
+      hipLaunchKernelGGL((batch_sweep_kernel<RR, 0>), dim3(L.blocks), dim3(kSweepTD * kSweepTD), \
+                         0, st, inst, L);                                                       \
+    else                                                                                        \
+      hipLaunchKernelGGL((batch_sweep_kernel<RR, 1>), dim3(L.blocks), dim3(kSweepTD * kSweepTD), \
+                         0, st, inst, L);                                                       \
+    break;
+  switch (R) {
+    GNM_BS_CASE(1) GNM_BS_CASE(2) GNM_BS_CASE(3) GNM_BS_CASE(4) GNM_BS_CASE(5) GNM_BS_CASE(6)
+    GNM_BS_CASE(7) GNM_BS_CASE(8) GNM_BS_CASE(9) GNM_BS_CASE(10) GNM_BS_CASE(11)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef GNM_BS_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_reduce_rows(const BatchInst* inst, const BatchLaunch& L, hipStream_t st) {
+  if (L.count == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_reduce_rows_kernel, dim3(L.blocks), dim3(256), 0, st, inst, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_gram(int nt, const BatchInst* inst, const BatchLaunch& L, hipStream_t st) {
+  if (L.count == 0) return hipSuccess;
+#define GNM_BG_CASE(NT)                                                                          \
+  case NT:                                                                                       \
+    hipLaunchKernelGGL((batch_gram_kernel<NT>), dim3(L.blocks), dim3(256), 0, st, inst, L);       \
+    break;
+  switch (nt) {
+    GNM_BG_CASE(1) GNM_BG_CASE(2) GNM_BG_CASE(3) GNM_BG_CASE(4) GNM_BG_CASE(5) GNM_BG_CASE(6)
+    GNM_BG_CASE(7) GNM_BG_CASE(8) GNM_BG_CASE(9) GNM_BG_CASE(10) GNM_BG_CASE(11)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef GNM_BG_CASE
+  return hipGetLastError();
 }
 
 }  // namespace gnm

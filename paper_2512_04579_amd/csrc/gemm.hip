@@ -22,6 +22,7 @@
 // (measured with a one-wave probe).  A lane that loads k-values kl..kl+V-1 feeds
 // them to V consecutive MFMAs; the k-permutation this induces is the same
 // for A and B, so the sum is unchanged.
+#include "batch.hpp"
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -122,16 +123,16 @@ __device__ __forceinline__ void store_tiles(const Acc (&acc)[NT], T* __restrict_
 }
 
 template <typename T, int NT, bool VEC, int KW>
-__global__ void __launch_bounds__(256) contract_kernel(ContractArgs<T> a) {
+__device__ __forceinline__ void contract_block(const ContractArgs<T>& a, int bx, int by,
+                                               unsigned char* contract_smem) {
   using MT = Mfma<T>;
   using Acc = typename MT::Acc;
   constexpr int V = MT::kLaneK, STEP = MT::kStep;
-  extern __shared__ unsigned char contract_smem[];
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int r16 = lane & 15, kq = lane >> 4;
-  const int row_base = (blockIdx.x * (4 / KW) + wave / KW) * 16;
+  const int row_base = (bx * (4 / KW) + wave / KW) * 16;
   const int kw = wave % KW;
-  const int kbeg = blockIdx.y * a.split_len;
+  const int kbeg = by * a.split_len;
   const int kend = min(a.K, kbeg + a.split_len);
 
   const int row = row_base + r16;
@@ -180,9 +181,41 @@ __global__ void __launch_bounds__(256) contract_kernel(ContractArgs<T> a) {
     }
   }
 
-  T* out = a.out + static_cast<int64_t>(blockIdx.y) * a.split_stride;
+  T* out = a.out + static_cast<int64_t>(by) * a.split_stride;
   store_tiles<T, Acc, NT, KW>(acc, reinterpret_cast<T*>(contract_smem), row_base, a.rows, out,
                               a.ldo, a.ocols, [](int q, int j) { return MT::out_row(q, j); });
+}
+
+template <typename T, int NT, bool VEC, int KW>
+__global__ void __launch_bounds__(256) contract_kernel(ContractArgs<T> a) {
+  extern __shared__ unsigned char contract_smem[];
+  contract_block<T, NT, VEC, KW>(a, blockIdx.x, blockIdx.y, contract_smem);
+}
+
+// Batched float32 contractions of an iteration: MODE 0 forms the G = W W^T
+// partials, MODE 1 the Jacobian J = S G^{-1}.  tile = by * row_blocks + bx.
+template <int MODE>
+__device__ __forceinline__ ContractArgs<float> batch_contract_args(const BatchInst& b) {
+  if constexpr (MODE == 0)
+    return ContractArgs<float>{b.n, b.n, b.n, b.K, b.W, b.ldw, nullptr, nullptr, 0, b.W, b.ldw,
+                               b.gsplit_len, b.gpart, b.npad,
+                               static_cast<int64_t>(b.n) * b.npad, b.npad};
+  else
+    return ContractArgs<float>{b.m, b.m, b.n, b.n, b.S, b.npad, nullptr, nullptr, 0, b.Ginv,
+                               b.npad, b.n, b.J, b.n, 0, b.n};
+}
+
+template <int NT, int MODE>
+__global__ void __launch_bounds__(256) batch_contract_kernel(const BatchInst* __restrict__ inst,
+                                                             BatchLaunch L) {
+  extern __shared__ unsigned char contract_smem[];
+  for (int w = blockIdx.x; w < L.count; w += gridDim.x) {
+    const BatchItem it = L.items[w];
+    const ContractArgs<float> a = batch_contract_args<MODE>(inst[it.inst]);
+    const int rb = (a.rows + 15) / 16;  // KW = 4: one 16-row tile per block
+    contract_block<float, NT, true, 4>(a, it.tile % rb, it.tile / rb, contract_smem);
+    __syncthreads();
+  }
 }
 
 template <typename T, int NT>
@@ -244,16 +277,32 @@ using f32x4 = float __attribute__((ext_vector_type(4)));
 constexpr int kBf16Step = 32;
 
 // W (n x K, ldw) -> hi and lo bf16 planes (n x kpad), zero beyond K.
-__global__ void __launch_bounds__(256) split_bf16_kernel(int K, int kpad, const float* __restrict__ W,
-                                                         int64_t ldw, __bf16* __restrict__ hi,
-                                                         __bf16* __restrict__ lo) {
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  const int row = blockIdx.y;
+__device__ __forceinline__ void split_bf16_block(int K, int kpad, const float* __restrict__ W,
+                                                 int64_t ldw, __bf16* __restrict__ hi,
+                                                 __bf16* __restrict__ lo, int bx, int row) {
+  const int k = bx * 256 + threadIdx.x;
   if (k >= kpad) return;
   const float v = k < K ? W[row * ldw + k] : 0.0f;
   const __bf16 h = static_cast<__bf16>(v);
   hi[static_cast<int64_t>(row) * kpad + k] = h;
   lo[static_cast<int64_t>(row) * kpad + k] = static_cast<__bf16>(v - static_cast<float>(h));
+}
+
+__global__ void __launch_bounds__(256) split_bf16_kernel(int K, int kpad, const float* __restrict__ W,
+                                                         int64_t ldw, __bf16* __restrict__ hi,
+                                                         __bf16* __restrict__ lo) {
+  split_bf16_block(K, kpad, W, ldw, hi, lo, blockIdx.x, blockIdx.y);
+}
+
+// Batched: tile = row * ceil(kpad / 256) + k-chunk.
+__global__ void __launch_bounds__(256) batch_split_bf16_kernel(const BatchInst* __restrict__ inst,
+                                                               BatchLaunch L) {
+  for (int w = blockIdx.x; w < L.count; w += gridDim.x) {
+    const BatchItem it = L.items[w];
+    const BatchInst& b = inst[it.inst];
+    const int xb = (b.kpad + 255) / 256;
+    split_bf16_block(b.K, b.kpad, b.W, b.ldw, b.Wh, b.Wl, it.tile % xb, it.tile / xb);
+  }
 }
 
 // Block = 4 waves over 64 TM rows and one k-slice.  The B operand of each
@@ -265,10 +314,10 @@ __global__ void __launch_bounds__(256) split_bf16_kernel(int K, int kpad, const 
 // streams from HBM into registers one step ahead and is converted to bf16
 // (and split into hi + lo) in registers.  One barrier per step.
 template <int TERMS, int NT, int TM, bool VEC>
-__global__ void __launch_bounds__(256) contract_bf16_kernel(
+__device__ __forceinline__ void contract_bf16_block(
     int m, int n, int K, const float* __restrict__ R, int64_t ldr, const float* __restrict__ r0,
     const __bf16* __restrict__ Bh, const __bf16* __restrict__ Bl, int kpad, int split_len,
-    float* __restrict__ part, int npad) {
+    float* __restrict__ part, int npad, int bx, int by) {
   constexpr int PLANES = TERMS == 3 ? 2 : 1;
   constexpr int NCOL = 16 * NT;
   constexpr int CHUNKS = PLANES * NCOL * (kBf16Step / 8);  // 16-byte pieces per stage
@@ -277,8 +326,8 @@ __global__ void __launch_bounds__(256) contract_bf16_kernel(
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1), wave = tid / kWave;
   const int r16 = lane & 15, kq = lane >> 4;
-  const int row_base = blockIdx.x * 64 * TM + wave * 16 * TM;
-  const int kbeg = blockIdx.y * split_len;
+  const int row_base = bx * 64 * TM + wave * 16 * TM;
+  const int kbeg = by * split_len;
   const int kend = min(K, kbeg + split_len);
   const int nstep = (kend - kbeg + kBf16Step - 1) / kBf16Step;
 
@@ -399,7 +448,7 @@ __global__ void __launch_bounds__(256) contract_bf16_kernel(
       __syncthreads();
     }
   }
-  float* out = part + static_cast<int64_t>(blockIdx.y) * m * npad;
+  float* out = part + static_cast<int64_t>(by) * m * npad;
 #pragma unroll
   for (int t = 0; t < TM; ++t)
 #pragma unroll
@@ -409,6 +458,30 @@ __global__ void __launch_bounds__(256) contract_bf16_kernel(
 #pragma unroll
         for (int tn = 0; tn < NT; ++tn) out[row * npad + 16 * tn + r16] = acc[t][tn][j];
     }
+}
+
+template <int TERMS, int NT, int TM, bool VEC>
+__global__ void __launch_bounds__(256) contract_bf16_kernel(
+    int m, int n, int K, const float* __restrict__ R, int64_t ldr, const float* __restrict__ r0,
+    const __bf16* __restrict__ Bh, const __bf16* __restrict__ Bl, int kpad, int split_len,
+    float* __restrict__ part, int npad) {
+  contract_bf16_block<TERMS, NT, TM, VEC>(m, n, K, R, ldr, r0, Bh, Bl, kpad, split_len, part, npad,
+                                          blockIdx.x, blockIdx.y);
+}
+
+// Batched S = (R - r0 1^T) W^T partials, BF16x3; tile = split * row_blocks + row block.
+template <int NT>
+__global__ void __launch_bounds__(256) batch_contract_bf16_kernel(const BatchInst* __restrict__ inst,
+                                                                  BatchLaunch L) {
+  for (int w = blockIdx.x; w < L.count; w += gridDim.x) {
+    const BatchItem it = L.items[w];
+    const BatchInst& b = inst[it.inst];
+    const int rb = (b.m + 64 * kBf16RowTiles - 1) / (64 * kBf16RowTiles);
+    contract_bf16_block<3, NT, kBf16RowTiles, true>(b.m, b.n, b.K, b.R, b.ldr, b.r0, b.Wh, b.Wl,
+                                                    b.kpad, b.split_len, b.part, b.npad,
+                                                    it.tile % rb, it.tile / rb);
+    __syncthreads();
+  }
 }
 
 template <int TERMS, bool VEC>
@@ -443,6 +516,54 @@ hipError_t launch_contract(const ContractArgs<float>& a, int nsplit, hipStream_t
 }
 hipError_t launch_contract(const ContractArgs<double>& a, int nsplit, hipStream_t st) {
   return contract_typed(a, nsplit, st);
+}
+
+int batch_contract_row_blocks(int rows) { return (rows + 15) / 16; }
+int batch_bf16_row_blocks(int m) { return (m + 64 * kBf16RowTiles - 1) / (64 * kBf16RowTiles); }
+
+hipError_t launch_batch_contract(int mode, int nt, const BatchInst* inst, const BatchLaunch& L,
+                                 hipStream_t st) {
+  if (L.count == 0) return hipSuccess;
+#define GNM_BC_CASE(NT)                                                                          \
+  case NT:                                                                                       \
+    if (mode == 0)                                                                               \
+      hipLaunchKernelGGL((batch_contract_kernel<NT, 0>), dim3(L.blocks), dim3(256),             \
+                         (split_lds_bytes<float, NT>()), st, inst, L);                          \
+    else                                                                                         \
+      hipLaunchKernelGGL((batch_contract_kernel<NT, 1>), dim3(L.blocks), dim3(256),             \
+                         (split_lds_bytes<float, NT>()), st, inst, L);                          \
+    break;
+  switch (nt) {
+    GNM_BC_CASE(1) GNM_BC_CASE(2) GNM_BC_CASE(3) GNM_BC_CASE(4) GNM_BC_CASE(5) GNM_BC_CASE(6)
+    GNM_BC_CASE(7) GNM_BC_CASE(8) GNM_BC_CASE(9) GNM_BC_CASE(10) GNM_BC_CASE(11) GNM_BC_CASE(12)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef GNM_BC_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_split_bf16(const BatchInst* inst, const BatchLaunch& L, hipStream_t st) {
+  if (L.count == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_split_bf16_kernel, dim3(L.blocks), dim3(256), 0, st, inst, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_contract_bf16(int nt, const BatchInst* inst, const BatchLaunch& L,
+                                      hipStream_t st) {
+  if (L.count == 0) return hipSuccess;
+#define GNM_BB_CASE(NT)                                                                          \
+  case NT:                                                                                       \
+    hipLaunchKernelGGL((batch_contract_bf16_kernel<NT>), dim3(L.blocks), dim3(256), 0, st, inst, L); \
+    break;
+  switch (nt) {
+    GNM_BB_CASE(1) GNM_BB_CASE(2) GNM_BB_CASE(3) GNM_BB_CASE(4) GNM_BB_CASE(5) GNM_BB_CASE(6)
+    GNM_BB_CASE(7) GNM_BB_CASE(8) GNM_BB_CASE(9) GNM_BB_CASE(10) GNM_BB_CASE(11) GNM_BB_CASE(12)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef GNM_BB_CASE
+  return hipGetLastError();
 }
 
 hipError_t launch_split_bf16(int n, int K, int kpad, const float* W, int64_t ldw, __bf16* hi,

@@ -102,6 +102,34 @@ hipError_t launch_ggn(int dtype, int m, int n, const void* J, int64_t ldj, const
                       int64_t inc_r0, double lm_lambda, void* dU, void* work,
                       int32_t* status, hipStream_t st);
 
+// Batched iteration steps (batch.hpp); each launcher covers one shape class.
+struct BatchInst;
+struct BatchLaunch;
+int batch_sample_tiles(int n, int K);
+hipError_t launch_batch_sample(const BatchInst* inst, const BatchLaunch& L, double sigma,
+                               uint64_t stream_id, hipStream_t st);
+int batch_chain_group(int M);
+int batch_rollout_tiles(int M, int K);
+size_t batch_rollout_lds(int G, int N);
+hipError_t launch_batch_rollout(int G, const BatchInst* inst, const BatchLaunch& L,
+                                const gnmppi_problem& shared, int N_max, hipStream_t st);
+hipError_t launch_batch_line_search(int G, const BatchInst* inst, const BatchLaunch& L,
+                                    const gnmppi_problem& shared, int n_alpha, int N_max,
+                                    hipStream_t st);
+int batch_contract_row_blocks(int rows);
+int batch_bf16_row_blocks(int m);
+hipError_t launch_batch_contract(int mode, int nt, const BatchInst* inst, const BatchLaunch& L,
+                                 hipStream_t st);
+hipError_t launch_batch_split_bf16(const BatchInst* inst, const BatchLaunch& L, hipStream_t st);
+hipError_t launch_batch_contract_bf16(int nt, const BatchInst* inst, const BatchLaunch& L,
+                                      hipStream_t st);
+hipError_t launch_batch_reduce_sym(int mode, const BatchInst* inst, const BatchLaunch& L,
+                                   double lm_lambda, hipStream_t st);
+hipError_t launch_batch_sweep(int mode, int R, const BatchInst* inst, const BatchLaunch& L,
+                              hipStream_t st);
+hipError_t launch_batch_reduce_rows(const BatchInst* inst, const BatchLaunch& L, hipStream_t st);
+hipError_t launch_batch_gram(int nt, const BatchInst* inst, const BatchLaunch& L, hipStream_t st);
+
 // Warm-start perceptron I -> H -> H -> O (mlp.hip).
 int64_t mlp_param_count(int I, int H, int O);
 size_t mlp_workspace_bytes(int H, int O, int batch);

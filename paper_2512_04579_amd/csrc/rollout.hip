@@ -14,6 +14,7 @@
 // The chain kernel stages each step's rows in LDS and writes every row of
 // the block as one contiguous segment; the double-integrator kernel's lanes
 // already write consecutive columns.
+#include "batch.hpp"
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -238,15 +239,16 @@ __device__ __forceinline__ int xcd_logical_block() {
   return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
 }
 
+// Logical block g of one rollout launch: samples g kSpb .. g kSpb + kSpb - 1
+// (column K is the nominal).  ctl_raw: the dynamic LDS for staged controls.
 template <typename T, int G>
-__global__ void __launch_bounds__(256) rollout_chain_kernel(
+__device__ __forceinline__ void rollout_chain_block(
     ChainDev<T> cd, int N, const T* __restrict__ x0, const T* __restrict__ q,
     const T* __restrict__ r, const T* __restrict__ xref, const T* __restrict__ U,
     const T* __restrict__ W, int64_t ldw, int K, T* __restrict__ R, int64_t ldr,
-    T* __restrict__ C, T* __restrict__ r0, T* __restrict__ c0, int nblocks, int stage_ctl) {
+    T* __restrict__ C, T* __restrict__ r0, T* __restrict__ c0, int nblocks, int stage_ctl, int g,
+    unsigned char* ctl_raw) {
   constexpr int kSpb = kBlock / G;
-  extern __shared__ unsigned char ctl_raw[];
-  const int g = xcd_logical_block();
   if (g >= nblocks) return;  // whole padding block: no barrier is shared with it
   const int ncol = K + (c0 ? 1 : 0);
   const int grp = threadIdx.x / G;
@@ -300,6 +302,34 @@ __global__ void __launch_bounds__(256) rollout_chain_kernel(
       c0[0] = c;
     else
       C[col] = c;
+  }
+}
+
+template <typename T, int G>
+__global__ void __launch_bounds__(256) rollout_chain_kernel(
+    ChainDev<T> cd, int N, const T* __restrict__ x0, const T* __restrict__ q,
+    const T* __restrict__ r, const T* __restrict__ xref, const T* __restrict__ U,
+    const T* __restrict__ W, int64_t ldw, int K, T* __restrict__ R, int64_t ldr,
+    T* __restrict__ C, T* __restrict__ r0, T* __restrict__ c0, int nblocks, int stage_ctl) {
+  extern __shared__ unsigned char ctl_raw[];
+  rollout_chain_block<T, G>(cd, N, x0, q, r, xref, U, W, ldw, K, R, ldr, C, r0, c0, nblocks,
+                            stage_ctl, xcd_logical_block(), ctl_raw);
+}
+
+// Batched: item = (instance, logical block); controls always staged.
+template <int G>
+__global__ void __launch_bounds__(256) batch_rollout_kernel(const BatchInst* __restrict__ inst,
+                                                            BatchLaunch L, ChainDev<float> cd0) {
+  extern __shared__ unsigned char ctl_raw[];
+  for (int w = blockIdx.x; w < L.count; w += gridDim.x) {
+    const BatchItem it = L.items[w];
+    const BatchInst& b = inst[it.inst];
+    ChainDev<float> cd = cd0;
+    cd.M = b.M;
+    const int nblocks = ((b.K + 1) * G + kBlock - 1) / kBlock;
+    rollout_chain_block<float, G>(cd, b.N, b.x0, b.q, b.r, b.xref, b.U, b.W, b.ldw, b.K, b.R,
+                                  b.ldr, b.C, b.r0, b.c0, nblocks, 1, it.tile, ctl_raw);
+    __syncthreads();  // the next item reuses the LDS
   }
 }
 
@@ -408,13 +438,13 @@ __device__ __forceinline__ void line_select_and_apply(T* costs, int L, int n, T*
 }
 
 template <typename T, int G>
-__global__ void __launch_bounds__(1024) line_search_chain_kernel(
+__device__ __forceinline__ void line_search_chain_block(
     ChainDev<T> cd, int N, const T* __restrict__ x0, const T* __restrict__ q,
     const T* __restrict__ r, const T* __restrict__ xref, T* U, const T* __restrict__ dU,
-    const T* __restrict__ alpha, int L, T* __restrict__ Cout, double* info, int stage_ctl) {
+    const T* __restrict__ alpha, int L, T* __restrict__ Cout, double* info, int stage_ctl,
+    unsigned char* ctl_raw) {
   __shared__ T costs[64];
   __shared__ int jstar;
-  extern __shared__ unsigned char ctl_raw[];
   const int j = threadIdx.x / G;
   const int jj = j < L ? j : L - 1;
   const int n = 2 * N;
@@ -437,6 +467,32 @@ __global__ void __launch_bounds__(1024) line_search_chain_kernel(
   }
   if (j < L && (threadIdx.x & (G - 1)) == 0) costs[j] = c;
   line_select_and_apply(costs, L, n, U, dU, alpha, Cout, info, &jstar);
+}
+
+template <typename T, int G>
+__global__ void __launch_bounds__(1024) line_search_chain_kernel(
+    ChainDev<T> cd, int N, const T* __restrict__ x0, const T* __restrict__ q,
+    const T* __restrict__ r, const T* __restrict__ xref, T* U, const T* __restrict__ dU,
+    const T* __restrict__ alpha, int L, T* __restrict__ Cout, double* info, int stage_ctl) {
+  extern __shared__ unsigned char ctl_raw[];
+  line_search_chain_block<T, G>(cd, N, x0, q, r, xref, U, dU, alpha, L, Cout, info, stage_ctl,
+                                ctl_raw);
+}
+
+// Batched: item = instance; L * G threads.
+template <int G>
+__global__ void __launch_bounds__(1024) batch_line_search_kernel(const BatchInst* __restrict__ inst,
+                                                                 BatchLaunch Lw, ChainDev<float> cd0,
+                                                                 int L) {
+  extern __shared__ unsigned char ctl_raw[];
+  for (int w = blockIdx.x; w < Lw.count; w += gridDim.x) {
+    const BatchInst& b = inst[Lw.items[w].inst];
+    ChainDev<float> cd = cd0;
+    cd.M = b.M;
+    line_search_chain_block<float, G>(cd, b.N, b.x0, b.q, b.r, b.xref, b.U, b.dU, b.alpha, L,
+                                      nullptr, b.info, 1, ctl_raw);
+    __syncthreads();
+  }
 }
 
 template <typename T, int D>
@@ -586,6 +642,62 @@ hipError_t launch_rollout(const gnmppi_problem& p, const void* x0, const void* U
                                static_cast<const double*>(W), ldw, K, static_cast<double*>(R),
                                ldr, static_cast<double*>(C), static_cast<double*>(r0),
                                static_cast<double*>(c0), st);
+}
+
+int batch_chain_group(int M) { return chain_group(M); }
+
+int batch_rollout_tiles(int M, int K) {
+  const int G = chain_group(M);
+  return ((K + 1) * G + kBlock - 1) / kBlock;
+}
+
+size_t batch_rollout_lds(int G, int N) { return static_cast<size_t>(N) * 2 * (kBlock / G) * sizeof(float); }
+
+hipError_t launch_batch_rollout(int G, const BatchInst* inst, const BatchLaunch& L,
+                                const gnmppi_problem& shared, int N_max, hipStream_t st) {
+  if (L.count == 0) return hipSuccess;
+  const ChainDev<float> cd = chain_dev<float>(shared);
+  const size_t lds = batch_rollout_lds(G, N_max);
+  switch (G) {
+    case 4:
+      hipLaunchKernelGGL(batch_rollout_kernel<4>, dim3(L.blocks), dim3(kBlock), lds, st, inst, L, cd);
+      break;
+    case 8:
+      hipLaunchKernelGGL(batch_rollout_kernel<8>, dim3(L.blocks), dim3(kBlock), lds, st, inst, L, cd);
+      break;
+    case 16:
+      hipLaunchKernelGGL(batch_rollout_kernel<16>, dim3(L.blocks), dim3(kBlock), lds, st, inst, L, cd);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_line_search(int G, const BatchInst* inst, const BatchLaunch& Lw,
+                                    const gnmppi_problem& shared, int L, int N_max,
+                                    hipStream_t st) {
+  if (Lw.count == 0) return hipSuccess;
+  const ChainDev<float> cd = chain_dev<float>(shared);
+  const int threads = ((L * G + 63) / 64) * 64;
+  const size_t lds = static_cast<size_t>(N_max) * 2 * 2 * sizeof(float);
+  switch (G) {
+    case 4:
+      hipLaunchKernelGGL(batch_line_search_kernel<4>, dim3(Lw.blocks), dim3(threads), lds, st, inst,
+                         Lw, cd, L);
+      break;
+    case 8:
+      hipLaunchKernelGGL(batch_line_search_kernel<8>, dim3(Lw.blocks), dim3(threads), lds, st, inst,
+                         Lw, cd, L);
+      break;
+    case 16:
+      hipLaunchKernelGGL(batch_line_search_kernel<16>, dim3(Lw.blocks), dim3(threads), lds, st,
+                         inst, Lw, cd, L);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_line_search(const gnmppi_problem& p, const void* x0, void* U, const void* dU,

@@ -6,6 +6,7 @@
 // four normals (two Box-Muller pairs), FP64 into two.  Threads of a wave take
 // consecutive columns, so every store is a coalesced 256/512-byte row segment
 // of the sample-fastest W.
+#include "batch.hpp"
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -54,13 +55,13 @@ __device__ __forceinline__ void box_muller_f64(Philox4x32 x, double& z0, double&
   z1 = rad * s;
 }
 
+// Block (bx, by): draws bx * 256 + thread of the rows kRows by .. kRows by + kRows - 1.
 template <typename T>
-__global__ void __launch_bounds__(256) sample_kernel(int n, int Kdraw, T sigma, uint32_t k0,
-                                                     uint32_t k1, uint32_t s0, uint32_t s1,
-                                                     int antithetic, T* __restrict__ W,
-                                                     int64_t ldw) {
-  const int s = blockIdx.x * 256 + threadIdx.x;
-  const int b = blockIdx.y;
+__device__ __forceinline__ void sample_block(int n, int Kdraw, T sigma, uint32_t k0, uint32_t k1,
+                                             uint32_t s0, uint32_t s1, int antithetic,
+                                             T* __restrict__ W, int64_t ldw, int bx, int by) {
+  const int s = bx * 256 + threadIdx.x;
+  const int b = by;
   if (s >= Kdraw) return;
   const Philox4x32 x = philox4x32_10(Philox4x32{static_cast<uint32_t>(s), static_cast<uint32_t>(b), s0, s1}, k0, k1);
   constexpr int kRows = sizeof(T) == 4 ? 4 : 2;
@@ -83,6 +84,31 @@ __global__ void __launch_bounds__(256) sample_kernel(int n, int Kdraw, T sigma, 
 }
 
 template <typename T>
+__global__ void __launch_bounds__(256) sample_kernel(int n, int Kdraw, T sigma, uint32_t k0,
+                                                     uint32_t k1, uint32_t s0, uint32_t s1,
+                                                     int antithetic, T* __restrict__ W,
+                                                     int64_t ldw) {
+  sample_block<T>(n, Kdraw, sigma, k0, k1, s0, s1, antithetic, W, ldw, blockIdx.x, blockIdx.y);
+}
+
+// Batched: instance b draws with key b.seed and the stream id of the
+// iteration (the same numbers as a single-instance call with that seed);
+// tile = by * ceil(Kdraw / 256) + bx.
+__global__ void __launch_bounds__(256) batch_sample_kernel(const BatchInst* __restrict__ inst,
+                                                           BatchLaunch L, float sigma, uint32_t s0,
+                                                           uint32_t s1) {
+  for (int w = blockIdx.x; w < L.count; w += gridDim.x) {
+    const BatchItem it = L.items[w];
+    const BatchInst& b = inst[it.inst];
+    const int Kdraw = b.K / 2;
+    const int xb = (Kdraw + 255) / 256;
+    sample_block<float>(b.n, Kdraw, sigma, static_cast<uint32_t>(b.seed),
+                        static_cast<uint32_t>(b.seed >> 32), s0, s1, 1, b.W, b.ldw, it.tile % xb,
+                        it.tile / xb);
+  }
+}
+
+template <typename T>
 __global__ void __launch_bounds__(256) sigma_points_kernel(int n, T scale, T* __restrict__ W,
                                                            int64_t ldw) {
   const int s = blockIdx.x * 256 + threadIdx.x;
@@ -95,6 +121,17 @@ __global__ void __launch_bounds__(256) sigma_points_kernel(int n, T scale, T* __
 }
 
 }  // namespace
+
+int batch_sample_tiles(int n, int K) { return ((K / 2 + 255) / 256) * ((n + 3) / 4); }
+
+hipError_t launch_batch_sample(const BatchInst* inst, const BatchLaunch& L, double sigma,
+                               uint64_t stream_id, hipStream_t st) {
+  if (L.count == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_sample_kernel, dim3(L.blocks), dim3(256), 0, st, inst, L,
+                     static_cast<float>(sigma), static_cast<uint32_t>(stream_id),
+                     static_cast<uint32_t>(stream_id >> 32));
+  return hipGetLastError();
+}
 
 hipError_t launch_sample(int dtype, int n, int K, double sigma, uint64_t seed,
                          uint64_t stream_id, int antithetic, void* W, int64_t ldw,

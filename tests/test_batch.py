@@ -1,0 +1,155 @@
+"""Batched GN-MPPI over uneven chain instances (one enqueue per iteration,
+persistent launches per step and shape class).
+
+Parity: every instance of a small uneven batch -- masses 3..16 (all three
+lane-group classes), horizons 7..33 (several MFMA-tile and sweep classes),
+K 64..512 -- after one iteration against the FP64 oracle fed the same Philox
+stream (instance b uses key seed + b); after two iterations against the
+single-instance solver; graph replays against eager iterations; every tuning
+against the default one.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from _parity import assert_parity, rnd, round_problem
+from oracle import philox, solvers
+from paper_2512_04579_amd import _lib
+from paper_2512_04579_amd.batch import BatchGNMPPI, autotune
+from paper_2512_04579_amd.problem import DeviceProblem
+from paper_2512_04579_amd.solver import GNMPPI
+
+SHAPES = [(3, 7, 64), (4, 12, 96), (5, 20, 128), (8, 9, 256), (9, 33, 384), (16, 16, 512)]
+
+
+def _instances():
+    out = []
+    for i, (M, N, K) in enumerate(SHAPES):
+        prob, x0 = wl.chain_problem(n_masses=M, N=N, dt=0.05, seed=40 + i)
+        out.append((prob, x0, K))
+    return out
+
+
+def _settings():
+    return wl.SolverSettings(iters=3, K=0, sigma0=0.3, beta=0.9, sigma_min=1e-3, gamma=0.5,
+                             n_alpha=16, contraction="bf16x3")
+
+
+@pytest.mark.gpu
+def test_batch_first_iteration_matches_oracle():
+    inst = _instances()
+    st = _settings()
+    batch = BatchGNMPPI(inst, st, seed=11)
+    batch.step(0)
+    torch.cuda.synchronize()
+    status = batch.status.cpu().numpy()
+    info = batch.info.cpu().numpy()
+    assert (status == 0).all(), status
+    for b, (p, x0, K) in enumerate(inst):
+        rp = round_problem(p, "f32")
+        noise = lambda it, s, K=K, p=p, b=b: rnd(philox.perturbations(p.n, K, s, 11 + b, it, "f32"), "f32")  # noqa: E731
+        Uo, h = solvers.gn_mppi(rp, rnd(x0, "f32"), np.zeros(p.n), 1, noise, st.sigma0, beta=st.beta,
+                                sigma_min=st.sigma_min)
+        assert info[b, 0] == h.alpha[0], (b, info[b], h.alpha)
+        assert_parity([info[b, 1]], [h.cost[0]], "f32", f"instance {b} cost")
+        assert_parity(batch.controls(b).double().cpu().numpy(), Uo, "f32", f"instance {b} U", tol=1e-3)
+
+
+@pytest.mark.gpu
+def test_batch_matches_the_single_instance_solver():
+    inst = _instances()
+    st = _settings()
+    batch = BatchGNMPPI(inst, st, seed=21)
+    for it in range(2):
+        batch.step(it)
+    torch.cuda.synchronize()
+    for b, (p, x0, K) in enumerate(inst):
+        s1 = wl.SolverSettings(iters=2, K=K, sigma0=st.sigma0, beta=st.beta, sigma_min=st.sigma_min,
+                               gamma=st.gamma, n_alpha=st.n_alpha, contraction="bf16x3")
+        single = GNMPPI(DeviceProblem(p, "f32"), x0, s1, seed=21 + b, max_iters=2)
+        single.solve(2)
+        torch.cuda.synchronize()
+        costs, _, status = single.history(2)
+        assert (status == 0).all()
+        assert_parity([batch.info[b, 1].item()], [costs[1]], "f32", f"instance {b} cost")
+        assert_parity(batch.controls(b).double().cpu().numpy(), single.U.double().cpu().numpy(), "f32",
+                      f"instance {b} U", tol=1e-3)
+
+
+@pytest.mark.gpu
+def test_batch_graph_replays_match_eager_iterations():
+    inst = _instances()
+    st = _settings()
+    eager = BatchGNMPPI(inst, st, seed=5)
+    for it in range(2):
+        eager.step(it)
+    torch.cuda.synchronize()
+    U_ref, info_ref = eager.U.cpu().numpy(), eager.info.cpu().numpy()
+    g = BatchGNMPPI(inst, st, seed=5)
+    graph = g.capture(2)
+    for rep in range(3):
+        g.U.zero_()
+        g.info.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(g.U.cpu().numpy(), U_ref, err_msg=f"replay {rep}")
+        np.testing.assert_array_equal(g.info.cpu().numpy(), info_ref, err_msg=f"replay {rep}")
+
+
+@pytest.mark.gpu
+def test_batch_tunings_compute_the_same_iteration(tmp_path):
+    inst = _instances()
+    st = _settings()
+    ref = BatchGNMPPI(inst, st, seed=8)
+    ref.step(0)
+    torch.cuda.synchronize()
+    U_ref = ref.U.cpu().numpy()
+    for tuning in ({"contract_ksplit": 1, "rollout_blocks_per_cu": 1},
+                   {"contract_ksplit": 4, "contract_blocks_per_cu": 4, "small_blocks_per_cu": 1}):
+        b = BatchGNMPPI(inst, st, seed=8, tuning=tuning)
+        b.step(0)
+        torch.cuda.synchronize()
+        assert_parity(b.U.cpu().numpy(), U_ref, "f32", str(tuning))
+    b = BatchGNMPPI(inst, st, seed=8)
+    entry = autotune(b, space={"contract_ksplit": (1, 2), "rollout_blocks_per_cu": (1, 2)}, reps=1,
+                     cache=str(tmp_path / "tune.json"))
+    assert entry["candidates"] == 4 and entry["tuning"] == b.tuning
+    b.step(0)
+    torch.cuda.synchronize()
+    assert_parity(b.U.cpu().numpy(), U_ref, "f32", "autotuned")
+
+
+def test_batch_rejects_invalid_instances():
+    lib = _lib.load()
+    shared = _lib.GnmppiProblem(model=_lib.MODEL_CHAIN, dtype=_lib.F32, nx=0, nu=0, N=0, n_masses=0,
+                                dt=0.05, k_lin=1.0, k_cub=0.5, mass=1.0, q=None, r=None, x_ref=None)
+    arr = (_lib.GnmppiBatchInstance * 2)()
+    for a in arr:
+        a.n_masses, a.N, a.K = 8, 20, 128
+        a.x0 = a.q = a.r = a.x_ref = a.U = a.status = a.info = 0x1000
+    st = _lib.GnmppiBatchSettings(seed=1, gamma=0.5, n_alpha=16, reserved=0, lm_lambda=0.0)
+    tu = _lib.GnmppiBatchTuning()
+    args = lambda: (ctypes.byref(shared), 2, arr, ctypes.byref(st), ctypes.byref(tu))  # noqa: E731
+    ws = lib.gnmppi_batch_workspace(*args())
+    assert ws > 0
+    arr[1].K = 64  # K / 2 < n = 40: the antithetic pairs do not span the decisions
+    assert lib.gnmppi_batch_workspace(*args()) == 0
+    arr[1].K = 128
+    arr[1].n_masses = 2
+    assert lib.gnmppi_batch_workspace(*args()) == 0
+    arr[1].n_masses = 8
+    arr[1].N = 81
+    assert lib.gnmppi_batch_workspace(*args()) == 0
+    arr[1].N = 20
+    st.n_alpha = 65
+    assert lib.gnmppi_batch_workspace(*args()) == 0
+    st.n_alpha = 16
+    assert lib.gnmppi_batch_prepare(*args(), 0x1008, ws) == _lib.EINVAL          # misaligned
+    assert lib.gnmppi_batch_prepare(*args(), 0x1000, ws - 1) == _lib.ENOSPACE
+    assert lib.gnmppi_batch_iteration(*args(), 0x1000, ws, 0, 0.0, None) == _lib.EINVAL  # sigma
+    shared.dtype = _lib.F64
+    assert lib.gnmppi_batch_workspace(*args()) == 0
