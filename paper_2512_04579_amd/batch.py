@@ -156,7 +156,7 @@ def _batch_key(batch: BatchGNMPPI) -> str:
     return hashlib.sha256(json.dumps(shapes).encode()).hexdigest()[:16]
 
 
-def autotune(batch: BatchGNMPPI, space: dict | None = None, reps: int = 2, cache: str | None = CACHE,
+def autotune(batch: BatchGNMPPI, space: dict | None = None, reps: int = 3, cache: str | None = CACHE,
              log=None) -> dict:
     """Times every tuning in ``space`` (the product of its value lists) on one
     iteration of ``batch`` and sets the fastest.  U is restored after each
@@ -175,16 +175,21 @@ def autotune(batch: BatchGNMPPI, space: dict | None = None, reps: int = 2, cache
     for values in itertools.product(*(space[k] for k in names)):
         tuning = dict(zip(names, values))
         batch.set_tuning(tuning)
-        batch.step(0)  # warm-up
+        # timed as graph replays: an eager call also rebuilds the work tables
+        # on the host, which a captured iteration never does
+        graph = batch.capture(1)
+        graph.replay()  # warm-up
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
+        ms = 0.0
         for _ in range(reps):
             batch.U.copy_(U0)
-            batch.step(0)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
+            e0.record()
+            graph.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            ms += e0.elapsed_time(e1) / reps
+        del graph
         results.append((ms, tuning))
         if log:
             log(f"tuning {tuning}: {ms:.3f} ms/iteration")
