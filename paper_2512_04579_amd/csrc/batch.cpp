@@ -100,7 +100,7 @@ Plan make_plan(int count, const gnmppi_batch_instance* in, const gnmppi_batch_se
     d.split_len = spl * 32;
     d.gsplit = 1;
     d.gsplit_len = ksteps * 32;
-    d.hsplit = std::max(1, std::min(4, cdiv(d.m, 512)));
+    d.hsplit = std::max(1, std::min(16, cdiv(d.m, 128)));
     d.hchunk = cdiv(cdiv(d.m, d.hsplit), 4) * 4;
     d.hsplit = cdiv(d.m, d.hchunk);
     d.ldw = d.ldr = cdiv(d.K, 64) * 64;
@@ -111,9 +111,10 @@ Plan make_plan(int count, const gnmppi_batch_instance* in, const gnmppi_batch_se
     tiles[kReduceG][i] = d.n;
     tiles[kSweepG][i] = 1;
     tiles[kRollout][i] = batch_rollout_tiles(d.M, d.K);
-    tiles[kSplit][i] = cdiv(d.kpad, 256) * d.n;
+    tiles[kSplit][i] = 0;  // the sampler writes the bf16 planes itself
     tiles[kContractS][i] = batch_bf16_row_blocks(d.m) * d.nsplit;
-    tiles[kReduceS][i] = cdiv(d.m, 4) * cdiv(d.n, 64);
+    // one k-slice: the partial sum already is S (no reduction)
+    tiles[kReduceS][i] = d.nsplit > 1 ? cdiv(d.m, 4) * cdiv(d.n, 64) : 0;
     tiles[kJac][i] = batch_contract_row_blocks(d.m);
     tiles[kGramH][i] = d.hsplit;
     tiles[kReduceH][i] = d.n + 1;
@@ -154,6 +155,7 @@ Plan make_plan(int count, const gnmppi_batch_instance* in, const gnmppi_batch_se
       for (int i : kv.second)
         for (int t = 0; t < tiles[s][i]; ++t) pl.items.push_back(BatchItem{i, t});
       L.count = static_cast<int>(pl.items.size() - L.first);
+      if (L.count == 0) continue;
       L.blocks = std::max(1, std::min(L.count, cap(static_cast<Step>(s))));
       pl.launches.push_back(L);
     }
@@ -185,9 +187,10 @@ Plan make_plan(int count, const gnmppi_batch_instance* in, const gnmppi_batch_se
     d.c0 = reinterpret_cast<float*>(take(sizeof(float)));
     d.J = reinterpret_cast<float*>(take(sizeof(float) * static_cast<size_t>(d.m) * d.n));
     d.dU = reinterpret_cast<float*>(take(sizeof(float) * d.n));
-    d.S = reinterpret_cast<float*>(take(sizeof(float) * static_cast<size_t>(d.m) * d.npad));
     d.part = reinterpret_cast<float*>(
         take(sizeof(float) * static_cast<size_t>(d.nsplit) * d.m * d.npad));
+    d.S = d.nsplit > 1 ? reinterpret_cast<float*>(take(sizeof(float) * static_cast<size_t>(d.m) * d.npad))
+                       : d.part;
     d.gpart = reinterpret_cast<float*>(take(sizeof(float) * static_cast<size_t>(d.gsplit) * d.n * d.npad));
     d.Ginv = reinterpret_cast<float*>(take(sizeof(float) * d.n * d.npad));
     d.Wh = reinterpret_cast<__bf16*>(take(2 * static_cast<size_t>(d.n) * d.kpad));

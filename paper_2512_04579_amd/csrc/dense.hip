@@ -430,22 +430,32 @@ __device__ __forceinline__ void gram_chunk(int m, int n, const T* __restrict__ J
   f64x4 acc[NACC];
 #pragma unroll
   for (int q = 0; q < NACC; ++q) acc[q] = f64x4{0, 0, 0, 0};
-  for (int k0 = ibeg; k0 < iend; k0 += 4) {
+  // row k0 + kq of [J r0], columns 16 t + r16 (zero outside the chunk)
+  auto load = [&](int k0, T (&x)[NT]) {
     const int row = k0 + kq;
     const bool rv = row < iend;
-    double x[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int col = 16 * t + r16;
-      double v = 0.0;
+      T v = 0;
       if (rv) {
         if (col < n)
-          v = static_cast<double>(J[static_cast<int64_t>(row) * ldj + col]);
+          v = J[static_cast<int64_t>(row) * ldj + col];
         else if (col == n)
-          v = static_cast<double>(r0[static_cast<int64_t>(row) * inc]);
+          v = r0[static_cast<int64_t>(row) * inc];
       }
       x[t] = v;
     }
+  };
+  // the next step's rows are requested before this step's MFMAs
+  T cur[NT];
+  load(ibeg, cur);
+  for (int k0 = ibeg; k0 < iend; k0 += 4) {
+    T nxt[NT];
+    load(k0 + 4, nxt);
+    double x[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) x[t] = static_cast<double>(cur[t]);
     int q = 0;
 #pragma unroll
     for (int ta = 0; ta < NT; ++ta)
@@ -453,6 +463,8 @@ __device__ __forceinline__ void gram_chunk(int m, int n, const T* __restrict__ J
       for (int tb = 0; tb <= ta; ++tb, ++q)
         if ((q & 3) == wave)
           acc[q >> 2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[ta], x[tb], acc[q >> 2], 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) cur[t] = nxt[t];
   }
   double* out = part + static_cast<int64_t>(bx) * P * P;
   int q = 0;

@@ -56,10 +56,14 @@ __device__ __forceinline__ void box_muller_f64(Philox4x32 x, double& z0, double&
 }
 
 // Block (bx, by): draws bx * 256 + thread of the rows kRows by .. kRows by + kRows - 1.
+// With `hi` / `lo` (float32 only) the draws are also written as the hi + lo
+// bfloat16 planes (n x kpad, zero beyond K) that the BF16x3 contraction reads.
 template <typename T>
 __device__ __forceinline__ void sample_block(int n, int Kdraw, T sigma, uint32_t k0, uint32_t k1,
                                              uint32_t s0, uint32_t s1, int antithetic,
-                                             T* __restrict__ W, int64_t ldw, int bx, int by) {
+                                             T* __restrict__ W, int64_t ldw, int bx, int by,
+                                             __bf16* __restrict__ hi = nullptr,
+                                             __bf16* __restrict__ lo = nullptr, int kpad = 0) {
   const int s = bx * 256 + threadIdx.x;
   const int b = by;
   if (s >= Kdraw) return;
@@ -72,6 +76,7 @@ __device__ __forceinline__ void sample_block(int n, int Kdraw, T sigma, uint32_t
   } else {
     box_muller_f64(x, z[0], z[1]);
   }
+  const int K = antithetic ? 2 * Kdraw : Kdraw;
 #pragma unroll
   for (int t = 0; t < kRows; ++t) {
     const int row = kRows * b + t;
@@ -79,6 +84,23 @@ __device__ __forceinline__ void sample_block(int n, int Kdraw, T sigma, uint32_t
       const T v = sigma * z[t];
       W[row * ldw + s] = v;
       if (antithetic) W[row * ldw + s + Kdraw] = -v;
+      if constexpr (sizeof(T) == 4) {
+        if (hi != nullptr) {
+          const __bf16 h = static_cast<__bf16>(v);
+          const __bf16 l = static_cast<__bf16>(v - static_cast<float>(h));
+          const int64_t o = static_cast<int64_t>(row) * kpad;
+          hi[o + s] = h;
+          lo[o + s] = l;
+          if (antithetic) {  // -v splits into -h and -l exactly
+            hi[o + s + Kdraw] = -h;
+            lo[o + s + Kdraw] = -l;
+          }
+          for (int pz = s; pz < kpad - K; pz += Kdraw) {  // zero padding up to kpad
+            hi[o + K + pz] = __bf16(0.0f);
+            lo[o + K + pz] = __bf16(0.0f);
+          }
+        }
+      }
     }
   }
 }
@@ -104,7 +126,7 @@ __global__ void __launch_bounds__(256) batch_sample_kernel(const BatchInst* __re
     const int xb = (Kdraw + 255) / 256;
     sample_block<float>(b.n, Kdraw, sigma, static_cast<uint32_t>(b.seed),
                         static_cast<uint32_t>(b.seed >> 32), s0, s1, 1, b.W, b.ldw, it.tile % xb,
-                        it.tile / xb);
+                        it.tile / xb, b.Wh, b.Wl, b.kpad);
   }
 }
 
