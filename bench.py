@@ -107,6 +107,43 @@ def cpu_baseline(w, budget_s: float):
             "sample_steps_per_s": its * (st.K + 1 + st.n_alpha) * p.N / el}
 
 
+def bench_sweep(args):
+    """GN-MPPI iterations/s of the chain16 workload at K in {512 .. 8192} and
+    N in {20, 50, 80} (graph-timed, 50 iterations per point)."""
+    import dataclasses
+
+    import torch
+
+    import workloads as wl
+    from paper_2512_04579_amd.problem import DeviceProblem
+    from paper_2512_04579_amd.solver import GNMPPI
+
+    base = wl.c2()
+    rows = []
+    for N in (20, 50, 80):
+        prob, x0 = wl.chain_problem(n_masses=16, N=N, dt=0.05, seed=0)
+        dp = DeviceProblem(prob, "f32")
+        for K in (512, 1024, 2048, 4096, 8192):
+            st = dataclasses.replace(base.settings, K=K)
+            solver = GNMPPI(dp, x0, st, seed=1, max_iters=51, overlap=True)
+            graph = solver.capture(50)
+            graph.replay()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            graph.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 50
+            rows.append({"N": N, "K": K, "m": prob.m, "n": prob.n, "us_per_iter": 1e3 * ms,
+                         "iters_per_s": 1e3 / ms,
+                         "sample_steps_per_s": (K + 1 + st.n_alpha) * N / (ms * 1e-3)})
+            del graph, solver
+    return {"metric": METRIC, "unit": "iters/s", "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "chain16 RK4 dt=0.05 scaling sweep over K and N", "name": "c2-sweep"},
+            "timed_with": "HIP graph replays of 50 iterations per point", "sweep": rows}
+
+
 def bench_batched(args):
     """The batched form: ``--batch-count`` chain instances with M in 4..16,
     N in 20..80 and K in {512, 1024, 2048, 4096} (seeded), one GN-MPPI
@@ -213,6 +250,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"],
                     help="c3 = 1024 uneven chain instances through the batched iteration")
     ap.add_argument("--batch-count", type=int, default=1024, help="instances of the c3 workload")
+    ap.add_argument("--sweep", action="store_true",
+                    help="chain16 scaling curves: iterations/s at K in 512..8192 and N in 20, 50, 80")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-gap", action="store_true")
@@ -250,6 +289,9 @@ def main():
 
     if args.workload == "c3":
         print(json.dumps(bench_batched(args)))
+        return
+    if args.sweep:
+        print(json.dumps(bench_sweep(args)))
         return
     w = wl.get(args.workload)
     p, st = w.problem, w.settings
