@@ -671,15 +671,17 @@ hipError_t jacobian_typed(int m, int n, int K, const T* R, int64_t ldr, const T*
     e = gram_inverse_typed<T>(pl, n, K, W, ldw, wk, part, pl.nsplit, split_stride, m, status, st);
     if (e != hipSuccess) return e;
   }
-  // with a ready G the rank check belongs to gnmppi_perturbation_gram's own
-  // status word and the S reduction reports success here
-  hipLaunchKernelGGL(reduce_rows_kernel<T>, rgrid, dim3(256), 0, st, part, pl.nsplit, split_stride,
-                     pl.npad, m, n, 1.0, S, pl.npad, ready ? status : nullptr);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  // J = S G^{-1} = S (G^{-1})^T: the same contraction over the decision index
-  ContractArgs<T> c2{m, m, n, n, S, pl.npad, nullptr, nullptr, 0, Ginv, pl.npad, n,
+  // J = S G^{-1} = S (G^{-1})^T: the same contraction over the decision index,
+  // with S = the sum of the k-slice partials added while the A operand loads.
+  // With a ready G the rank check belongs to gnmppi_perturbation_gram's own
+  // status word and this contraction reports success.
+  (void)S;
+  (void)rgrid;
+  ContractArgs<T> c2{m, m, n, n, part, pl.npad, nullptr, nullptr, 0, Ginv, pl.npad, n,
                      J, ldj, 0, n};
+  c2.asplit = pl.nsplit;
+  c2.asplit_stride = split_stride;
+  c2.status = ready ? status : nullptr;
   return launch_contract(c2, 1, st);
 }
 

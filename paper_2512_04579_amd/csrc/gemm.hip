@@ -138,13 +138,16 @@ __device__ __forceinline__ void contract_block(const ContractArgs<T>& a, int bx,
   const int row = row_base + r16;
   const T* arow;
   T asub = 0;
+  int nsum = 1;  // partials added while loading (rows of A only)
   if (row < a.m) {
     arow = a.A + row * a.lda;
     asub = a.asub ? a.asub[row] : T(0);
+    nsum = a.asplit;
   } else if (row < a.rows) {
     arow = a.A2 + (row - a.m) * a.lda2;
-  } else {  // past the last row: read a valid row, never stored
-    arow = a.B;
+  } else {  // past the last row: read row 0 of A (present in every partial), never stored
+    arow = a.m > 0 ? a.A : a.A2;
+    nsum = a.m > 0 ? a.asplit : 1;
   }
   const T* bcol[NT];
   bool bzero[NT];
@@ -165,6 +168,12 @@ __device__ __forceinline__ void contract_block(const ContractArgs<T>& a, int bx,
       const int kl = k0 + kq * V;
       T av[V], bv[NT][V];
       load_lane_k<T, VEC>(arow, kl, kend, full, av);
+      for (int sp = 1; sp < nsum; ++sp) {
+        T part[V];
+        load_lane_k<T, VEC>(arow + sp * a.asplit_stride, kl, kend, full, part);
+#pragma unroll
+        for (int t = 0; t < V; ++t) av[t] += part[t];
+      }
 #pragma unroll
       for (int t = 0; t < V; ++t) av[t] = (kl + t < kend) ? av[t] - asub : T(0);
 #pragma unroll
@@ -181,6 +190,7 @@ __device__ __forceinline__ void contract_block(const ContractArgs<T>& a, int bx,
     }
   }
 
+  if (a.status != nullptr && bx == 0 && by == 0 && threadIdx.x == 0) *a.status = GNMPPI_OK;
   T* out = a.out + static_cast<int64_t>(by) * a.split_stride;
   store_tiles<T, Acc, NT, KW>(acc, reinterpret_cast<T*>(contract_smem), row_base, a.rows, out,
                               a.ldo, a.ocols, [](int q, int j) { return MT::out_row(q, j); });

@@ -29,7 +29,9 @@ hipError_t launch_mppi_update(int dtype, int n, int K, const void* C, const void
 
 // out[y] = A B^T over k in [y split_len, (y+1) split_len) for y < nsplit.
 // Rows r < m come from A (minus asub[r] when asub is set), rows m <= r < rows
-// from A2; output columns are the ncol rows of B, written up to ocols.
+// from A2; output columns are the ncol rows of B, written up to ocols.  With
+// asplit > 1, A is itself a sum of asplit partials asplit_stride apart (added
+// in order while loading).  status (optional) is set to GNMPPI_OK by block 0.
 template <typename T>
 struct ContractArgs {
   int m, rows, ncol, K;
@@ -45,6 +47,9 @@ struct ContractArgs {
   int64_t ldo;
   int64_t split_stride;
   int ocols;
+  int asplit = 1;
+  int64_t asplit_stride = 0;
+  int32_t* status = nullptr;
 };
 // Waves per block that share one 16-row output tile of launch_contract and
 // split its k-steps between them (the planner sizes k-splits with it).

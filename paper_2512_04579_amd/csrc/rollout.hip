@@ -166,6 +166,46 @@ struct StagedSink {
   }
 };
 
+// DirectSink stores each lane's residual entries straight to R: for a fixed
+// row the sample groups of a block write consecutive columns, which meet in
+// L2 before they go to HBM.  No LDS and no barrier per step.
+template <typename T>
+struct DirectSink {
+  T* R;
+  int64_t ldr;
+  T* r0;
+  int K, col, M;
+  bool valid;
+  __device__ __forceinline__ void step(int k, int i, bool has_mass, bool first, T e0, T e1, T e2,
+                                       T e3, T f0, T f1) {
+    if (!valid) return;
+    const int64_t base = static_cast<int64_t>(k) * (4 * M + 2);
+    T* p;
+    int64_t ld;
+    if (col < K) {
+      p = R + col;
+      ld = ldr;
+    } else {
+      if (r0 == nullptr) return;
+      p = r0;
+      ld = 1;
+    }
+    if (has_mass) {
+      p[(base + 2 * i) * ld] = e0;
+      p[(base + 2 * i + 1) * ld] = e1;
+      p[(base + 2 * M + 2 * i) * ld] = e2;
+      p[(base + 2 * M + 2 * i + 1) * ld] = e3;
+    }
+    if (first) {
+      p[(base + 4 * M) * ld] = f0;
+      p[(base + 4 * M + 1) * ld] = f1;
+    }
+  }
+};
+
+// Residual rows go through StagedSink (false) or DirectSink (true).
+constexpr bool kDirectResidualStores = false;
+
 // Rolls out one sample on the G lanes of its group and returns the group's
 // cost 1/2 ||r||^2 (identical in every lane of the group).  All lanes of the
 // wave must call this together (the DPP shifts read neighbouring lanes).
@@ -271,7 +311,10 @@ __device__ __forceinline__ void rollout_chain_block(
     __syncthreads();
     CtrlStaged<T> ctrl{ctl, kSpb, grp};
     T c;
-    if (R != nullptr || r0 != nullptr) {
+    if ((R != nullptr || r0 != nullptr) && kDirectResidualStores) {
+      DirectSink<T> sink{R, ldr, r0, K, col, cd.M, valid};
+      c = chain_rollout<T, G>(cd, N, x0, q, r, xref, ctrl, sink);
+    } else if (R != nullptr || r0 != nullptr) {
       __shared__ T tile[2][StagedSink<T, G>::kRows][kSpb];
       StagedSink<T, G> sink{tile, R, ldr, r0, K, col0, cd.M, grp};
       c = chain_rollout<T, G>(cd, N, x0, q, r, xref, ctrl, sink);
