@@ -107,7 +107,7 @@ Plan make_plan(int count, const gnmppi_batch_instance* in, const gnmppi_batch_se
     d.seed = set->seed + static_cast<uint64_t>(i);
     pl.N_max = std::max(pl.N_max, d.N);
     tiles[kSample][i] = batch_sample_tiles(d.n, d.K);
-    tiles[kGramW][i] = batch_contract_row_blocks(d.n) * d.gsplit;
+    tiles[kGramW][i] = batch_contract_row_blocks(d.n, 0) * d.gsplit;
     tiles[kReduceG][i] = d.n;
     tiles[kSweepG][i] = 1;
     tiles[kRollout][i] = batch_rollout_tiles(d.M, d.K);
@@ -115,7 +115,7 @@ Plan make_plan(int count, const gnmppi_batch_instance* in, const gnmppi_batch_se
     tiles[kContractS][i] = batch_bf16_row_blocks(d.m) * d.nsplit;
     // one k-slice: the partial sum already is S (no reduction)
     tiles[kReduceS][i] = d.nsplit > 1 ? cdiv(d.m, 4) * cdiv(d.n, 64) : 0;
-    tiles[kJac][i] = batch_contract_row_blocks(d.m);
+    tiles[kJac][i] = batch_contract_row_blocks(d.m, 1);
     tiles[kGramH][i] = d.hsplit;
     tiles[kReduceH][i] = d.n + 1;
     tiles[kSweepH][i] = 1;

@@ -215,16 +215,22 @@ __device__ __forceinline__ ContractArgs<float> batch_contract_args(const BatchIn
                                b.npad, b.n, b.J, b.n, 0, b.n};
 }
 
+// G (K = samples, few rows): four waves split the k-steps of one 16-row tile;
+// J (K' = n, many rows): one wave per 16-row tile, four tiles per block.
+template <int MODE>
+constexpr int batch_contract_kw() { return MODE == 0 ? 4 : 1; }
+
 template <int NT, int MODE>
 __global__ void __launch_bounds__(256) batch_contract_kernel(const BatchInst* __restrict__ inst,
                                                              BatchLaunch L) {
+  constexpr int KW = batch_contract_kw<MODE>();
   extern __shared__ unsigned char contract_smem[];
   for (int w = blockIdx.x; w < L.count; w += gridDim.x) {
     const BatchItem it = L.items[w];
     const ContractArgs<float> a = batch_contract_args<MODE>(inst[it.inst]);
-    const int rb = (a.rows + 15) / 16;  // KW = 4: one 16-row tile per block
-    contract_block<float, NT, true, 4>(a, it.tile % rb, it.tile / rb, contract_smem);
-    __syncthreads();
+    const int rb = (a.rows + 64 / KW - 1) / (64 / KW);
+    contract_block<float, NT, true, KW>(a, it.tile % rb, it.tile / rb, contract_smem);
+    if constexpr (KW > 1) __syncthreads();  // the next item reuses the LDS
   }
 }
 
@@ -321,8 +327,9 @@ __global__ void __launch_bounds__(256) batch_split_bf16_kernel(const BatchInst* 
 // CU traffic for B is a quarter of what per-wave loads would move; the LDS
 // stage is laid out [plane][k-group of 8][column] so that the 16 lanes of a
 // fragment read 256 contiguous bytes.  The A operand (fp32 residual rows)
-// streams from HBM into registers one step ahead and is converted to bf16
-// (and split into hi + lo) in registers.  One barrier per step.
+// streams from HBM into registers two steps ahead (kept raw until its step, so
+// no load is waited on early), is shifted by r0 and converted to bf16 (and
+// split into hi + lo) in registers.  One barrier per step.
 template <int TERMS, int NT, int TM, bool VEC>
 __device__ __forceinline__ void contract_bf16_block(
     int m, int n, int K, const float* __restrict__ R, int64_t ldr, const float* __restrict__ r0,
@@ -377,7 +384,9 @@ __device__ __forceinline__ void contract_bf16_block(
       }
     }
   };
-  // this lane's 8 A values of row tile t for the step at k0, minus r0
+  // this lane's 8 raw A values of row tile t for the step at k0 (zero past
+  // kend); the r0 shift is applied where they are used, so that nothing waits
+  // on the loads before the step that consumes them
   auto load_a = [&](int k0, float (&a)[TM][8]) {
     const int kl = k0 + 8 * kq;
     if (VEC && k0 + kBf16Step <= kend) {
@@ -397,10 +406,6 @@ __device__ __forceinline__ void contract_bf16_block(
 #pragma unroll
         for (int e = 0; e < 8; ++e) a[t][e] = (kl + e < kend) ? arow[t][kl + e] : 0.0f;
     }
-#pragma unroll
-    for (int t = 0; t < TM; ++t)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) a[t][e] = (kl + e < kend) ? a[t][e] - asub[t] : 0.0f;
   };
 
   f32x4 acc[TM][NT];
@@ -410,28 +415,30 @@ __device__ __forceinline__ void contract_bf16_block(
     for (int tn = 0; tn < NT; ++tn) acc[t][tn] = f32x4{0, 0, 0, 0};
 
   if (nstep > 0) {
+    // A two steps ahead (HBM latency), B one step ahead (L2 -> LDS)
     bf16x8 breg[PER_THREAD];
-    float a[TM][8];
+    float a0[TM][8], a1[TM][8];
     load_b(kbeg, breg);
-    load_a(kbeg, a);
+    load_a(kbeg, a0);
+    if (nstep > 1) load_a(kbeg + kBf16Step, a1);
     store_b(0, breg);
     __syncthreads();
     for (int s = 0; s < nstep; ++s) {
       const int k0 = kbeg + s * kBf16Step;
       const bool more = s + 1 < nstep;
-      float an[TM][8];
-      if (more) {
-        load_b(k0 + kBf16Step, breg);
-        load_a(k0 + kBf16Step, an);
-      }
+      float a2[TM][8];
+      if (more) load_b(k0 + kBf16Step, breg);
+      if (s + 2 < nstep) load_a(k0 + 2 * kBf16Step, a2);
       const int buf = s & 1;
+      const int kl = k0 + 8 * kq;
       bf16x8 ah[TM], al[TM];
 #pragma unroll
       for (int t = 0; t < TM; ++t)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          ah[t][e] = static_cast<__bf16>(a[t][e]);
-          if constexpr (TERMS == 3) al[t][e] = static_cast<__bf16>(a[t][e] - static_cast<float>(ah[t][e]));
+          const float v = (kl + e < kend) ? a0[t][e] - asub[t] : 0.0f;
+          ah[t][e] = static_cast<__bf16>(v);
+          if constexpr (TERMS == 3) al[t][e] = static_cast<__bf16>(v - static_cast<float>(ah[t][e]));
         }
 #pragma unroll
       for (int tn = 0; tn < NT; ++tn) {
@@ -448,13 +455,14 @@ __device__ __forceinline__ void contract_bf16_block(
           }
         }
       }
-      if (more) {
-        store_b(buf ^ 1, breg);
+      if (more) store_b(buf ^ 1, breg);
 #pragma unroll
-        for (int t = 0; t < TM; ++t)
+      for (int t = 0; t < TM; ++t)
 #pragma unroll
-          for (int e = 0; e < 8; ++e) a[t][e] = an[t][e];
-      }
+        for (int e = 0; e < 8; ++e) {
+          a0[t][e] = a1[t][e];
+          a1[t][e] = a2[t][e];
+        }
       __syncthreads();
     }
   }
@@ -528,7 +536,9 @@ hipError_t launch_contract(const ContractArgs<double>& a, int nsplit, hipStream_
   return contract_typed(a, nsplit, st);
 }
 
-int batch_contract_row_blocks(int rows) { return (rows + 15) / 16; }
+int batch_contract_row_blocks(int rows, int mode) {
+  return mode == 0 ? (rows + 15) / 16 : (rows + 63) / 64;
+}
 int batch_bf16_row_blocks(int m) { return (m + 64 * kBf16RowTiles - 1) / (64 * kBf16RowTiles); }
 
 hipError_t launch_batch_contract(int mode, int nt, const BatchInst* inst, const BatchLaunch& L,
@@ -540,8 +550,8 @@ hipError_t launch_batch_contract(int mode, int nt, const BatchInst* inst, const 
       hipLaunchKernelGGL((batch_contract_kernel<NT, 0>), dim3(L.blocks), dim3(256),             \
                          (split_lds_bytes<float, NT>()), st, inst, L);                          \
     else                                                                                         \
-      hipLaunchKernelGGL((batch_contract_kernel<NT, 1>), dim3(L.blocks), dim3(256),             \
-                         (split_lds_bytes<float, NT>()), st, inst, L);                          \
+      hipLaunchKernelGGL((batch_contract_kernel<NT, 1>), dim3(L.blocks), dim3(256), 0, st,      \
+                         inst, L);                                                              \
     break;
   switch (nt) {
     GNM_BC_CASE(1) GNM_BC_CASE(2) GNM_BC_CASE(3) GNM_BC_CASE(4) GNM_BC_CASE(5) GNM_BC_CASE(6)

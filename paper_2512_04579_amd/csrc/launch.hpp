@@ -121,7 +121,7 @@ hipError_t launch_batch_rollout(int G, const BatchInst* inst, const BatchLaunch&
 hipError_t launch_batch_line_search(int G, const BatchInst* inst, const BatchLaunch& L,
                                     const gnmppi_problem& shared, int n_alpha, int N_max,
                                     hipStream_t st);
-int batch_contract_row_blocks(int rows);
+int batch_contract_row_blocks(int rows, int mode);
 int batch_bf16_row_blocks(int m);
 hipError_t launch_batch_contract(int mode, int nt, const BatchInst* inst, const BatchLaunch& L,
                                  hipStream_t st);

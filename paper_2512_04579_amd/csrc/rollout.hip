@@ -125,22 +125,24 @@ struct NoSink {
   __device__ __forceinline__ void step(int, int, bool, bool, T, T, T, T, T, T) {}
 };
 
-// StagedSink collects one step of residual rows of the block's samples in an
-// LDS tile (rows x samples, double-buffered) and then stores every row as one
-// contiguous segment of the sample-fastest R (or into r0 for the nominal
-// column).  One barrier per step; all threads of the block must call it.
-template <typename T, int G>
+// StagedSink collects the residual rows of the block's samples in an LDS
+// tile (F steps x rows x samples, double-buffered) and every F steps (and at
+// the last step) stores each row as one contiguous segment of the
+// sample-fastest R (or into r0 for the nominal column).  One barrier per F
+// steps; all threads of the block must call it.
+template <typename T, int G, int F>
 struct StagedSink {
   static constexpr int kSpb = kBlock / G;        // samples per block
   static constexpr int kRows = 4 * G + 2;        // >= rows per step (4 M + 2)
-  T (*tile)[kRows][kSpb];                        // [2][kRows][kSpb] in LDS
+  T (*tile)[F][kRows][kSpb];                     // [2][F][kRows][kSpb] in LDS
   T* R;
   int64_t ldr;
   T* r0;
-  int K, col0, M, grp;
+  int K, col0, M, grp, N;
   __device__ __forceinline__ void step(int k, int i, bool has_mass, bool first, T e0, T e1, T e2,
                                        T e3, T f0, T f1) {
-    T (*t)[kSpb] = tile[k & 1];
+    const int buf = (k / F) & 1, j = k % F;
+    T (*t)[kSpb] = tile[buf][j];
     if (has_mass) {
       t[2 * i][grp] = e0;
       t[2 * i + 1][grp] = e1;
@@ -151,20 +153,32 @@ struct StagedSink {
       t[4 * M][grp] = f0;
       t[4 * M + 1][grp] = f1;
     }
+    if (j != F - 1 && k != N - 1) return;  // uniform: flush every F steps and at the end
     __syncthreads();
     const int rows = 4 * M + 2;
-    const int64_t base = static_cast<int64_t>(k) * rows;
-    for (int idx = threadIdx.x; idx < rows * kSpb; idx += kBlock) {
-      const int row = idx / kSpb, s = idx % kSpb;
-      const int c = col0 + s;
-      if (c < K) {
-        if (R) R[(base + row) * ldr + c] = t[row][s];
-      } else if (c == K && r0) {
-        r0[base + row] = t[row][s];
+    for (int jj = 0; jj <= j; ++jj) {
+      const int64_t base = static_cast<int64_t>(k - j + jj) * rows;
+      for (int idx = threadIdx.x; idx < rows * kSpb; idx += kBlock) {
+        const int row = idx / kSpb, s = idx % kSpb;
+        const int c = col0 + s;
+        const T v = tile[buf][jj][row][s];
+        if (c < K) {
+          if (R) R[(base + row) * ldr + c] = v;
+        } else if (c == K && r0) {
+          r0[base + row] = v;
+        }
       }
     }
   }
 };
+
+// Steps per flush of StagedSink: about 24 KB of LDS per buffer.
+template <typename T, int G>
+constexpr int staged_flush_steps() {
+  constexpr int per_step = (4 * G + 2) * (kBlock / G) * static_cast<int>(sizeof(T));
+  constexpr int f = 24576 / per_step;
+  return f < 1 ? 1 : (f > 8 ? 8 : f);
+}
 
 // DirectSink stores each lane's residual entries straight to R: for a fixed
 // row the sample groups of a block write consecutive columns, which meet in
@@ -281,7 +295,7 @@ __device__ __forceinline__ int xcd_logical_block() {
 
 // Logical block g of one rollout launch: samples g kSpb .. g kSpb + kSpb - 1
 // (column K is the nominal).  ctl_raw: the dynamic LDS for staged controls.
-template <typename T, int G>
+template <typename T, int G, int FL>
 __device__ __forceinline__ void rollout_chain_block(
     ChainDev<T> cd, int N, const T* __restrict__ x0, const T* __restrict__ q,
     const T* __restrict__ r, const T* __restrict__ xref, const T* __restrict__ U,
@@ -289,6 +303,8 @@ __device__ __forceinline__ void rollout_chain_block(
     T* __restrict__ C, T* __restrict__ r0, T* __restrict__ c0, int nblocks, int stage_ctl, int g,
     unsigned char* ctl_raw) {
   constexpr int kSpb = kBlock / G;
+  // residual staging tile of StagedSink (one allocation for both control paths)
+  __shared__ T tile[2][FL][StagedSink<T, G, FL>::kRows][kSpb];
   if (g >= nblocks) return;  // whole padding block: no barrier is shared with it
   const int ncol = K + (c0 ? 1 : 0);
   const int grp = threadIdx.x / G;
@@ -315,8 +331,7 @@ __device__ __forceinline__ void rollout_chain_block(
       DirectSink<T> sink{R, ldr, r0, K, col, cd.M, valid};
       c = chain_rollout<T, G>(cd, N, x0, q, r, xref, ctrl, sink);
     } else if (R != nullptr || r0 != nullptr) {
-      __shared__ T tile[2][StagedSink<T, G>::kRows][kSpb];
-      StagedSink<T, G> sink{tile, R, ldr, r0, K, col0, cd.M, grp};
+      StagedSink<T, G, FL> sink{tile, R, ldr, r0, K, col0, cd.M, grp, N};
       c = chain_rollout<T, G>(cd, N, x0, q, r, xref, ctrl, sink);
     } else {
       NoSink sink;
@@ -333,8 +348,7 @@ __device__ __forceinline__ void rollout_chain_block(
   CtrlPerturbed<T> ctrl{U, W, ldw, (nominal || W == nullptr) ? -1 : col};
   T c;
   if (R != nullptr || r0 != nullptr) {
-    __shared__ T tile[2][StagedSink<T, G>::kRows][kSpb];
-    StagedSink<T, G> sink{tile, R, ldr, r0, K, g * kSpb, cd.M, grp};
+    StagedSink<T, G, FL> sink{tile, R, ldr, r0, K, g * kSpb, cd.M, grp, N};
     c = chain_rollout<T, G>(cd, N, x0, q, r, xref, ctrl, sink);
   } else {
     NoSink sink;
@@ -355,11 +369,14 @@ __global__ void __launch_bounds__(256) rollout_chain_kernel(
     const T* __restrict__ W, int64_t ldw, int K, T* __restrict__ R, int64_t ldr,
     T* __restrict__ C, T* __restrict__ r0, T* __restrict__ c0, int nblocks, int stage_ctl) {
   extern __shared__ unsigned char ctl_raw[];
-  rollout_chain_block<T, G>(cd, N, x0, q, r, xref, U, W, ldw, K, R, ldr, C, r0, c0, nblocks,
-                            stage_ctl, xcd_logical_block(), ctl_raw);
+  rollout_chain_block<T, G, staged_flush_steps<T, G>()>(cd, N, x0, q, r, xref, U, W, ldw, K, R,
+                                                        ldr, C, r0, c0, nblocks, stage_ctl,
+                                                        xcd_logical_block(), ctl_raw);
 }
 
-// Batched: item = (instance, logical block); controls always staged.
+// Batched: item = (instance, logical block); controls always staged.  Fewer
+// steps per flush than a single launch: several blocks share each CU.
+constexpr int kBatchFlushSteps = 2;
 template <int G>
 __global__ void __launch_bounds__(256) batch_rollout_kernel(const BatchInst* __restrict__ inst,
                                                             BatchLaunch L, ChainDev<float> cd0) {
@@ -370,8 +387,9 @@ __global__ void __launch_bounds__(256) batch_rollout_kernel(const BatchInst* __r
     ChainDev<float> cd = cd0;
     cd.M = b.M;
     const int nblocks = ((b.K + 1) * G + kBlock - 1) / kBlock;
-    rollout_chain_block<float, G>(cd, b.N, b.x0, b.q, b.r, b.xref, b.U, b.W, b.ldw, b.K, b.R,
-                                  b.ldr, b.C, b.r0, b.c0, nblocks, 1, it.tile, ctl_raw);
+    rollout_chain_block<float, G, kBatchFlushSteps>(cd, b.N, b.x0, b.q, b.r, b.xref, b.U, b.W,
+                                                    b.ldw, b.K, b.R, b.ldr, b.C, b.r0, b.c0,
+                                                    nblocks, 1, it.tile, ctl_raw);
     __syncthreads();  // the next item reuses the LDS
   }
 }
