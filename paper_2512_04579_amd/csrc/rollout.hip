@@ -134,7 +134,10 @@ template <typename T, int G, int F>
 struct StagedSink {
   static constexpr int kSpb = kBlock / G;        // samples per block
   static constexpr int kRows = 4 * G + 2;        // >= rows per step (4 M + 2)
-  T (*tile)[F][kRows][kSpb];                     // [2][F][kRows][kSpb] in LDS
+  // row stride kSpb + 1: the G lanes of a sample write rows 2i of one column,
+  // which a stride of kSpb would put in a single LDS bank
+  static constexpr int kLd = kSpb + 1;
+  T (*tile)[F][kRows][kLd];                      // [2][F][kRows][kLd] in LDS
   T* R;
   int64_t ldr;
   T* r0;
@@ -142,7 +145,7 @@ struct StagedSink {
   __device__ __forceinline__ void step(int k, int i, bool has_mass, bool first, T e0, T e1, T e2,
                                        T e3, T f0, T f1) {
     const int buf = (k / F) & 1, j = k % F;
-    T (*t)[kSpb] = tile[buf][j];
+    T (*t)[kLd] = tile[buf][j];
     if (has_mass) {
       t[2 * i][grp] = e0;
       t[2 * i + 1][grp] = e1;
@@ -175,7 +178,7 @@ struct StagedSink {
 // Steps per flush of StagedSink: about 24 KB of LDS per buffer.
 template <typename T, int G>
 constexpr int staged_flush_steps() {
-  constexpr int per_step = (4 * G + 2) * (kBlock / G) * static_cast<int>(sizeof(T));
+  constexpr int per_step = (4 * G + 2) * (kBlock / G + 1) * static_cast<int>(sizeof(T));
   constexpr int f = 24576 / per_step;
   return f < 1 ? 1 : (f > 8 ? 8 : f);
 }
@@ -304,7 +307,7 @@ __device__ __forceinline__ void rollout_chain_block(
     unsigned char* ctl_raw) {
   constexpr int kSpb = kBlock / G;
   // residual staging tile of StagedSink (one allocation for both control paths)
-  __shared__ T tile[2][FL][StagedSink<T, G, FL>::kRows][kSpb];
+  __shared__ T tile[2][FL][StagedSink<T, G, FL>::kRows][StagedSink<T, G, FL>::kLd];
   if (g >= nblocks) return;  // whole padding block: no barrier is shared with it
   const int ncol = K + (c0 ? 1 : 0);
   const int grp = threadIdx.x / G;
