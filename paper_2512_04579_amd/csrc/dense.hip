@@ -49,16 +49,26 @@ __device__ __forceinline__ void reduce_sym_row(const TP* __restrict__ part, int 
   const int j = threadIdx.x;
   if (j > i) return;
   const TP* src = part + static_cast<int64_t>(row0 + i) * ldp + j;
-  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  // 16 independent loads per round (one L2 round trip per 16 partials), then
+  // a fixed-order pairwise sum of the 16 accumulators
+  constexpr int U = 16;
+  double acc[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) acc[u] = 0.0;
   int sp = 0;
-  for (; sp + 4 <= nsplit; sp += 4) {
-    s0 += static_cast<double>(src[(sp + 0) * split_stride]);
-    s1 += static_cast<double>(src[(sp + 1) * split_stride]);
-    s2 += static_cast<double>(src[(sp + 2) * split_stride]);
-    s3 += static_cast<double>(src[(sp + 3) * split_stride]);
+  for (; sp + U <= nsplit; sp += U) {
+    TP v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = src[(sp + u) * split_stride];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] += static_cast<double>(v[u]);
   }
-  for (; sp < nsplit; ++sp) s0 += static_cast<double>(src[sp * split_stride]);
-  double s = (s0 + s1) + (s2 + s3);
+  for (; sp < nsplit; ++sp) acc[0] += static_cast<double>(src[sp * split_stride]);
+#pragma unroll
+  for (int w = U / 2; w >= 1; w /= 2)
+#pragma unroll
+    for (int u = 0; u < w; ++u) acc[u] += acc[u + w];
+  double s = acc[0];
   if (i == j && i < npiv) s += diag_shift;
   out[static_cast<int64_t>(i) * P + j] = s;
   out[static_cast<int64_t>(j) * P + i] = s;
