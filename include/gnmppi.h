@@ -76,9 +76,10 @@ extern "C" {
  * MC: J = (dR W^T) / (K sigma2), the Monte-Carlo mean of Eq. (10) itself. */
 #define GNMPPI_JAC_LS 0
 #define GNMPPI_JAC_MC 1
-/* Flag for GNMPPI_JAC_LS: G^{-1} is already in `work`, computed from the same
- * W by gnmppi_perturbation_gram (possibly on another stream, ordered before
- * this call by the caller), so only S and J = S G^{-1} are formed; the rank
+/* Flag for GNMPPI_JAC_LS: G^{-1} (and, for F32, the bf16 planes of W) is
+ * already in `work`, computed from the same W by gnmppi_perturbation_gram
+ * (possibly on another stream, ordered before this call by the caller), so
+ * only S and J = S G^{-1} are formed; the rank
  * check is then reported in gnmppi_perturbation_gram's status word and this
  * call writes GNMPPI_OK to its own. */
 #define GNMPPI_JAC_GRAM_READY 0x100
@@ -90,6 +91,16 @@ extern "C" {
  * stays on the FP32 contraction.  The two flags are mutually exclusive. */
 #define GNMPPI_JAC_BF16 0x200
 #define GNMPPI_JAC_BF16X3 0x400
+/* Flags for GNMPPI_JAC_LS | GNMPPI_JAC_GRAM_READY that split the call in
+ * two, so that a caller can order the stream that ran
+ * gnmppi_perturbation_gram before the second half only: S_ONLY forms the
+ * k-slice partial sums of S = dR W^T in `work` and writes neither J nor the
+ * status word; a later APPLY_ONLY call with the same dtype, m, n, K, work
+ * and other method bits forms J = S G^{-1} from them (R and W are not read)
+ * and writes GNMPPI_OK to its status word.  The two flags are mutually
+ * exclusive. */
+#define GNMPPI_JAC_S_ONLY 0x800
+#define GNMPPI_JAC_APPLY_ONLY 0x1000
 
 /* Problem data (Sec. 2).  Vectors are device arrays of the problem's dtype. */
 typedef struct gnmppi_problem {
@@ -178,8 +189,9 @@ int gnmppi_reconstruct_jacobian(int32_t dtype, int32_t m, int32_t n, int32_t K,
                                 int32_t *status, void *stream);
 
 /* The W-only half of the LS reconstruction: G = W W^T and its inverse (the
- * second-moment matrix that replaces Sigma in Eq. (10)), written into `work`
- * (the Jacobian workspace, same size rule) for a later
+ * second-moment matrix that replaces Sigma in Eq. (10)) and, for F32, the
+ * bf16 hi / lo planes of W that a BF16 sample contraction reads, written
+ * into `work` (the Jacobian workspace, same size rule) for a later
  * gnmppi_reconstruct_jacobian(..., GNMPPI_JAC_LS | GNMPPI_JAC_GRAM_READY, ...)
  * with the same dtype, n, K, W and work.  Because it does not depend on the
  * rollout, it can run concurrently with gnmppi_rollout on a second stream.
@@ -191,9 +203,11 @@ int gnmppi_perturbation_gram(int32_t dtype, int32_t m, int32_t n, int32_t K, con
 /* ---- a5: Generalized Gauss-Newton step (Eq. (13), Sec. 4.2) -------------
  * dU = -(J^T J + lm_lambda I)^{-1} J^T r0 for Phi = 1/2 ||.||^2, i.e. the
  * minimiser of the GGN subproblem.  J: m x n row-major (ldj), r0: m entries
- * with stride inc_r0.  J^T J and J^T r0 are accumulated and factored by
- * Cholesky in double precision; dU is written in dtype.  A non-positive
- * pivot sets *status = GNMPPI_ENOTPD and dU = 0.  1 <= n <= 192.
+ * with stride inc_r0.  J^T J and J^T r0 are accumulated in double precision
+ * and the system is solved there by the symmetric sweep operator (no
+ * pivoting; for an SPD matrix its pivots are the Cholesky pivots); dU is
+ * written in dtype.  A pivot at or below n 2^-52 max_i H_ii sets
+ * *status = GNMPPI_ENOTPD and dU = 0.  1 <= n <= 192.
  * `work`: at least gnmppi_ggn_workspace(...) bytes, 256-byte aligned. */
 size_t gnmppi_ggn_workspace(int32_t dtype, int32_t m, int32_t n);
 int gnmppi_ggn_step(int32_t dtype, int32_t m, int32_t n, const void *J,

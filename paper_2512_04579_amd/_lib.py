@@ -19,6 +19,7 @@ MODEL_DOUBLE_INTEGRATOR, MODEL_CHAIN = 1, 2
 JAC_LS, JAC_MC = 0, 1
 JAC_GRAM_READY = 0x100
 JAC_BF16, JAC_BF16X3 = 0x200, 0x400
+JAC_S_ONLY, JAC_APPLY_ONLY = 0x800, 0x1000
 OK, EINVAL, EHIP, ENOTPD, ERANK, ENONFINITE, ENOSPACE = 0, -1, -2, -3, -4, -5, -6
 
 

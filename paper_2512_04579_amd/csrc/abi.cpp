@@ -105,8 +105,13 @@ int gnmppi_reconstruct_jacobian(int32_t dtype, int32_t m, int32_t n, int32_t K, 
   if (ldr < K || ldw < K || ldj < n) return GNMPPI_EINVAL;
   const int32_t base = method & 0xff, flags = method & ~0xff;
   if (base != GNMPPI_JAC_LS && base != GNMPPI_JAC_MC) return GNMPPI_EINVAL;
-  if (flags & ~(GNMPPI_JAC_GRAM_READY | GNMPPI_JAC_BF16 | GNMPPI_JAC_BF16X3)) return GNMPPI_EINVAL;
+  if (flags & ~(GNMPPI_JAC_GRAM_READY | GNMPPI_JAC_BF16 | GNMPPI_JAC_BF16X3 | GNMPPI_JAC_S_ONLY |
+                GNMPPI_JAC_APPLY_ONLY))
+    return GNMPPI_EINVAL;
   if ((flags & GNMPPI_JAC_GRAM_READY) && base != GNMPPI_JAC_LS) return GNMPPI_EINVAL;
+  if ((flags & (GNMPPI_JAC_S_ONLY | GNMPPI_JAC_APPLY_ONLY)) && !(flags & GNMPPI_JAC_GRAM_READY))
+    return GNMPPI_EINVAL;
+  if ((flags & GNMPPI_JAC_S_ONLY) && (flags & GNMPPI_JAC_APPLY_ONLY)) return GNMPPI_EINVAL;
   if ((flags & GNMPPI_JAC_BF16) && (flags & GNMPPI_JAC_BF16X3)) return GNMPPI_EINVAL;
   if ((flags & (GNMPPI_JAC_BF16 | GNMPPI_JAC_BF16X3)) && dtype != GNMPPI_F32) return GNMPPI_EINVAL;
   if (base == GNMPPI_JAC_MC && (!(sigma2 > 0.0) || !std::isfinite(sigma2))) return GNMPPI_EINVAL;

@@ -73,10 +73,10 @@ class GNMPPI:
                  sampler: str = "gaussian", max_iters: int | None = None, overlap: bool = False):
         self.p = dprob
         # G = W W^T and its inverse depend only on W: with ``overlap`` they are
-        # factored on a side stream while the rollout runs (LS estimator only).
-        # Worth it inside a captured graph (the chain16 N=50 iteration drops
-        # from 241 to 207 us); with eager launches the cross-stream waits cost
-        # more than the overlap saves, hence off by default.
+        # factored on a side stream while the rollout and the sample
+        # contraction S run (LS estimator only).  Worth it inside a captured
+        # graph; with eager launches the cross-stream waits cost more than
+        # the overlap saves, hence off by default.
         self.overlap = overlap and settings.jacobian == "ls"
         self.side = torch.cuda.Stream(device=dprob.device) if self.overlap else None
         self.s = settings
@@ -128,19 +128,31 @@ class GNMPPI:
         else:
             _lib.gnmppi_sample(W, sig, self.seed, it, antithetic=self.s.antithetic, K=K)
         if self.overlap:
-            main = torch.cuda.current_stream()
-            self.side.wait_stream(main)
-            with torch.cuda.stream(self.side):
-                _lib.gnmppi_perturbation_gram(W, self.work_j, self.m, self.status[it, 2:3], K)
+            sampled = torch.cuda.Event()
+            sampled.record()
         tick.next("rollout")
         _lib.gnmppi_rollout(self.p, self.x0, self.U, W, K, self.R[:, :K], self.C, self.r0, self.c0)
-        tick.next("jacobian")
-        method = self.method
         if self.overlap:
+            # enqueued after the rollout so that a captured graph keeps the
+            # rollout on the sampling queue and forks only the W-only work
+            self.side.wait_event(sampled)
+            with torch.cuda.stream(self.side):
+                _lib.gnmppi_perturbation_gram(W, self.work_j, self.m, self.status[it, 2:3], K)
+        tick.next("jacobian")
+        if self.overlap:
+            # S = dR W^T needs only the rollout; the join with the side stream
+            # comes just before J = S G^{-1}
+            method = self.method | _lib.JAC_GRAM_READY
+            _lib.gnmppi_reconstruct_jacobian(self.R[:, :K], self.r0, W, self.J, self.work_j,
+                                             method | _lib.JAC_S_ONLY, sig * sig,
+                                             self.status[it, 0:1], K)
             torch.cuda.current_stream().wait_stream(self.side)
-            method |= _lib.JAC_GRAM_READY
-        _lib.gnmppi_reconstruct_jacobian(self.R[:, :K], self.r0, W, self.J, self.work_j,
-                                         method, sig * sig, self.status[it, 0:1], K)
+            _lib.gnmppi_reconstruct_jacobian(self.R[:, :K], self.r0, W, self.J, self.work_j,
+                                             method | _lib.JAC_APPLY_ONLY, sig * sig,
+                                             self.status[it, 0:1], K)
+        else:
+            _lib.gnmppi_reconstruct_jacobian(self.R[:, :K], self.r0, W, self.J, self.work_j,
+                                             self.method, sig * sig, self.status[it, 0:1], K)
         tick.next("ggn_step")
         _lib.gnmppi_ggn_step(self.J, self.r0, self.s.lm_lambda, self.dU, self.work_g,
                              self.status[it, 1:2])

@@ -121,8 +121,12 @@ def test_other_entry_points_reject_bad_arguments():
     assert lib.gnmppi_reconstruct_jacobian(_lib.F32, 3300, 100, 4096, 0x100, 4096, 0x200, 0x300, 4096,
                                            1 | _lib.JAC_GRAM_READY, 0.1, 0x400, 100, 0x1000, ws, None,
                                            None) == _lib.EINVAL  # gram flag only for LS
-    assert lib.gnmppi_reconstruct_jacobian(_lib.F32, 3300, 100, 4096, 0x100, 4096, 0x200, 0x300, 4096,
-                                           0x800, 0.1, 0x400, 100, 0x1000, ws, None, None) == _lib.EINVAL
+    # the two-phase flags need LS + GRAM_READY and exclude each other; unknown bits are rejected
+    for method in (_lib.JAC_S_ONLY, _lib.JAC_APPLY_ONLY,
+                   _lib.JAC_GRAM_READY | _lib.JAC_S_ONLY | _lib.JAC_APPLY_ONLY,
+                   _lib.JAC_MC | _lib.JAC_GRAM_READY | _lib.JAC_S_ONLY, 0x2000):
+        assert lib.gnmppi_reconstruct_jacobian(_lib.F32, 3300, 100, 4096, 0x100, 4096, 0x200, 0x300, 4096,
+                                               method, 0.1, 0x400, 100, 0x1000, ws, None, None) == _lib.EINVAL
     wsd = lib.gnmppi_jacobian_workspace(_lib.F64, 3300, 100, 4096)
     assert lib.gnmppi_reconstruct_jacobian(_lib.F64, 3300, 100, 4096, 0x100, 4096, 0x200, 0x300, 4096,
                                            _lib.JAC_BF16, 0.0, 0x400, 100, 0x1000, wsd, None, None) == _lib.EINVAL

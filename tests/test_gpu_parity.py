@@ -260,6 +260,46 @@ def test_jacobian_with_gram_factored_separately(case):
     assert_parity(host(J), jacobian.ls(R, W), dtype, "J (gram on a side stream)")
 
 
+@pytest.mark.parametrize("case", ["c2", "chain_f32_ragged"])
+@pytest.mark.parametrize("contraction", [0, _lib.JAC_BF16X3])
+def test_jacobian_in_two_phases_matches_one_call(case, contraction):
+    # S_ONLY on the main stream while the gram runs on a side stream, then
+    # APPLY_ONLY after the join: bit-identical to one GRAM_READY call
+    prob, dtype, K, sigma, R, W = _jacobian_inputs(case)
+    if dtype != "f32" and contraction:
+        pytest.skip("BF16 contractions are F32 only")
+    m, n = R.shape[0], W.shape[0]
+    Rd, Wd, r0d = padded(R[:, 1:], dtype), padded(W, dtype), to_dev(R[:, 0], dtype)
+    code = _lib.F32 if dtype == "f32" else _lib.F64
+    nbytes = _lib.gnmppi_jacobian_workspace(code, m, n, K)
+    method = _lib.JAC_LS | _lib.JAC_GRAM_READY | contraction
+    out = []
+    for split in (False, True):
+        work = torch.empty(nbytes, dtype=torch.uint8, device=device())
+        J = to_dev(np.zeros((m, n)), dtype)
+        st = torch.full((2,), 99, dtype=torch.int32, device=device())
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            _lib.gnmppi_perturbation_gram(Wd, work, m, st[1:2], K)
+        if split:
+            _lib.gnmppi_reconstruct_jacobian(Rd, r0d, Wd, J, work, method | _lib.JAC_S_ONLY, 0.0,
+                                             st[0:1], K)
+            torch.cuda.current_stream().wait_stream(side)
+            _sync()
+            assert host(st)[0] == 99  # S_ONLY writes no status
+            _lib.gnmppi_reconstruct_jacobian(Rd, r0d, Wd, J, work, method | _lib.JAC_APPLY_ONLY, 0.0,
+                                             st[0:1], K)
+        else:
+            torch.cuda.current_stream().wait_stream(side)
+            _lib.gnmppi_reconstruct_jacobian(Rd, r0d, Wd, J, work, method, 0.0, st[0:1], K)
+        _sync()
+        assert host(st).tolist() == [0, 0]
+        out.append(host(J))
+    np.testing.assert_array_equal(out[1], out[0])
+    assert_parity(out[1], jacobian.ls(R, W), dtype, "J (two phases)", tol=1e-3 if contraction else None)
+
+
 def test_perturbation_gram_reports_rank_deficiency():
     rng = np.random.default_rng(6)
     n, K = 12, 10
