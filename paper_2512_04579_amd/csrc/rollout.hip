@@ -92,16 +92,21 @@ struct CtrlLineStaged {
 
 // ---- chain ---------------------------------------------------------------
 
+// Right-hand side for mass i (lane i of the group).  The end mass moves with
+// the commanded velocity: its lane enters every step with v = u and inverse
+// mass im = 0, so dv = 0 keeps v = u through the RK4 stages and dp = v is
+// the commanded velocity with no per-stage select.
 template <typename T, int G>
-__device__ __forceinline__ void chain_rhs(T px, T py, T vx, T vy, T u0, T u1,
-                                          const ChainDev<T>& cd, bool first, bool free_mass,
-                                          T& dpx, T& dpy, T& dvx, T& dvy) {
+__device__ __forceinline__ void chain_rhs(T px, T py, T vx, T vy, const ChainDev<T>& cd, bool first,
+                                          T im, T& dpx, T& dpy, T& dvx, T& dvy) {
   T qx = 0, qy = 0;
   if constexpr (G > 1) {
     qx = dpp_move<kDppRowShr1>(px);
     qy = dpp_move<kDppRowShr1>(py);
   }
-  if (first) {  // link 1 is attached to the fixed anchor at the origin
+  // link 1 is attached to the fixed anchor at the origin; with G = 16 the
+  // group is a whole 16-lane row and the row shift already brings in zero
+  if (G < 16 && first) {
     qx = 0;
     qy = 0;
   }
@@ -113,10 +118,10 @@ __device__ __forceinline__ void chain_rhs(T px, T py, T vx, T vy, T u0, T u1,
     nx = dpp_move<kDppRowShl1>(tx);
     ny = dpp_move<kDppRowShl1>(ty);
   }
-  dpx = free_mass ? vx : u0;
-  dpy = free_mass ? vy : u1;
-  dvx = free_mass ? (nx - tx) * cd.inv_mass : T(0);
-  dvy = free_mass ? (ny - ty) * cd.inv_mass : T(0);
+  dpx = vx;
+  dpy = vy;
+  dvx = (nx - tx) * im;
+  dvy = (ny - ty) * im;
 }
 
 // Residual sinks of the chain rollout.  NoSink keeps only the cost.
@@ -247,6 +252,7 @@ __device__ __forceinline__ T chain_rollout(const ChainDev<T>& cd, int N,
   const T rvx = xref[2 * M + 2 * ii], rvy = xref[2 * M + 2 * ii + 1];
   const T wu0 = dsqrt(T(2) * r[0]), wu1 = dsqrt(T(2) * r[1]);
   const T h = cd.dt, hh = T(0.5) * cd.dt, h6 = cd.dt / T(6);
+  const T im = free_mass ? cd.inv_mass : T(0);
   T cost = 0;
   for (int k0 = 0; k0 < N; k0 += 4) {
 #pragma unroll
@@ -254,26 +260,26 @@ __device__ __forceinline__ T chain_rollout(const ChainDev<T>& cd, int N,
       const int k = k0 + t;
       if (k >= N) break;  // uniform: every lane has the same horizon
       const T u0 = ctrl(2 * k), u1 = ctrl(2 * k + 1);
+      if (!free_mass) {  // the end mass moves with the commanded velocity
+        vx = u0;
+        vy = u1;
+      }
       T a_px, a_py, a_vx, a_vy, b_px, b_py, b_vx, b_vy;
-      chain_rhs<T, G>(px, py, vx, vy, u0, u1, cd, first, free_mass, a_px, a_py, a_vx, a_vy);
+      chain_rhs<T, G>(px, py, vx, vy, cd, first, im, a_px, a_py, a_vx, a_vy);
       T s_px = a_px, s_py = a_py, s_vx = a_vx, s_vy = a_vy;  // running k1 + 2 k2 + 2 k3 + k4
-      chain_rhs<T, G>(px + hh * a_px, py + hh * a_py, vx + hh * a_vx, vy + hh * a_vy, u0, u1, cd,
-                      first, free_mass, b_px, b_py, b_vx, b_vy);
+      chain_rhs<T, G>(px + hh * a_px, py + hh * a_py, vx + hh * a_vx, vy + hh * a_vy, cd, first,
+                      im, b_px, b_py, b_vx, b_vy);
       s_px += T(2) * b_px; s_py += T(2) * b_py; s_vx += T(2) * b_vx; s_vy += T(2) * b_vy;
-      chain_rhs<T, G>(px + hh * b_px, py + hh * b_py, vx + hh * b_vx, vy + hh * b_vy, u0, u1, cd,
-                      first, free_mass, a_px, a_py, a_vx, a_vy);
+      chain_rhs<T, G>(px + hh * b_px, py + hh * b_py, vx + hh * b_vx, vy + hh * b_vy, cd, first,
+                      im, a_px, a_py, a_vx, a_vy);
       s_px += T(2) * a_px; s_py += T(2) * a_py; s_vx += T(2) * a_vx; s_vy += T(2) * a_vy;
-      chain_rhs<T, G>(px + h * a_px, py + h * a_py, vx + h * a_vx, vy + h * a_vy, u0, u1, cd,
-                      first, free_mass, b_px, b_py, b_vx, b_vy);
+      chain_rhs<T, G>(px + h * a_px, py + h * a_py, vx + h * a_vx, vy + h * a_vy, cd, first, im,
+                      b_px, b_py, b_vx, b_vy);
       s_px += b_px; s_py += b_py; s_vx += b_vx; s_vy += b_vy;
       px += h6 * s_px;
       py += h6 * s_py;
       vx += h6 * s_vx;
       vy += h6 * s_vy;
-      if (!free_mass) {  // the end mass moves with the commanded velocity
-        vx = u0;
-        vy = u1;
-      }
       const T e0 = wpx * (px - rpx), e1 = wpy * (py - rpy);
       const T e2 = wvx * (vx - rvx), e3 = wvy * (vy - rvy);
       const T f0 = wu0 * u0, f1 = wu1 * u1;
