@@ -517,8 +517,11 @@ def test_c1_solver_with_and_without_stream_overlap(overlap):
     assert abs(costs[0] - cstar) / cstar < 1e-10
 
 
+@pytest.mark.parametrize("overlap", [False, True])
 @pytest.mark.parametrize("name", ["c1", "c2"])
-def test_graph_replays_match_eager_iterations(name):
+def test_graph_replays_match_eager_iterations(name, overlap):
+    # with overlap the W-only half runs on a side stream with its own copy of
+    # W and a workspace per iteration: the same arithmetic, so bit-identical
     w = wl.get(name)
     dp = DeviceProblem(w.problem, w.dtype)
     eager = GNMPPI(dp, w.x0, w.settings, seed=5, max_iters=3)
@@ -526,7 +529,7 @@ def test_graph_replays_match_eager_iterations(name):
         eager.step(it)
     _sync()
     U_ref, info_ref = host(eager.U), host(eager.info)
-    g = GNMPPI(dp, w.x0, w.settings, seed=5, max_iters=3)
+    g = GNMPPI(dp, w.x0, w.settings, seed=5, max_iters=3, overlap=overlap)
     graph = g.capture(3)
     for rep in range(3):
         g.U.zero_()                      # fill kernel, outside the graph
