@@ -76,10 +76,9 @@ extern "C" {
  * MC: J = (dR W^T) / (K sigma2), the Monte-Carlo mean of Eq. (10) itself. */
 #define GNMPPI_JAC_LS 0
 #define GNMPPI_JAC_MC 1
-/* Flag for GNMPPI_JAC_LS: G^{-1} (and, for F32, the bf16 planes of W) is
- * already in `work`, computed from the same W by gnmppi_perturbation_gram
- * (possibly on another stream, ordered before this call by the caller), so
- * only S and J = S G^{-1} are formed; the rank
+/* Flag for GNMPPI_JAC_LS: G^{-1} is already in `work`, computed from the same
+ * W by gnmppi_perturbation_gram (possibly on another stream, ordered before
+ * this call by the caller), so only S and J = S G^{-1} are formed; the rank
  * check is then reported in gnmppi_perturbation_gram's status word and this
  * call writes GNMPPI_OK to its own. */
 #define GNMPPI_JAC_GRAM_READY 0x100
@@ -92,8 +91,9 @@ extern "C" {
 #define GNMPPI_JAC_BF16 0x200
 #define GNMPPI_JAC_BF16X3 0x400
 /* Flags for GNMPPI_JAC_LS | GNMPPI_JAC_GRAM_READY that split the call in
- * two, so that a caller can order the stream that ran
- * gnmppi_perturbation_gram before the second half only: S_ONLY forms the
+ * two, so that a caller needs to order the stream that ran
+ * gnmppi_perturbation_gram (which writes only the G region of `work`)
+ * before the second half only: S_ONLY forms the
  * k-slice partial sums of S = dR W^T in `work` and writes neither J nor the
  * status word; a later APPLY_ONLY call with the same dtype, m, n, K, work
  * and other method bits forms J = S G^{-1} from them (R and W are not read)
@@ -189,9 +189,8 @@ int gnmppi_reconstruct_jacobian(int32_t dtype, int32_t m, int32_t n, int32_t K,
                                 int32_t *status, void *stream);
 
 /* The W-only half of the LS reconstruction: G = W W^T and its inverse (the
- * second-moment matrix that replaces Sigma in Eq. (10)) and, for F32, the
- * bf16 hi / lo planes of W that a BF16 sample contraction reads, written
- * into `work` (the Jacobian workspace, same size rule) for a later
+ * second-moment matrix that replaces Sigma in Eq. (10)), written into `work`
+ * (the Jacobian workspace, same size rule) for a later
  * gnmppi_reconstruct_jacobian(..., GNMPPI_JAC_LS | GNMPPI_JAC_GRAM_READY, ...)
  * with the same dtype, n, K, W and work.  Because it does not depend on the
  * rollout, it can run concurrently with gnmppi_rollout on a second stream.

@@ -184,12 +184,63 @@ __device__ __forceinline__ void diag_pivot(double (&d4)[4], int nbv, double tol,
   }
 }
 
+// Pivots p and p + 1 together: with the 2 x 2 block B = [[a, b], [b, c]] of
+// D on them, D <- D_{\B} - Y Z^T where Z = columns p, p + 1 with rows p,
+// p + 1 replaced by -I and Y = Z B^{-1}, B^{-1} = [[c, -b], [-b, a]] / det.
+// One reciprocal per two pivots halves the latency chain of the single
+// pivots (the same block identity as between diagonal blocks).  The pivots
+// are a and the Schur complement det / a; both must exceed tol.
+template <int p>
+__device__ __forceinline__ void diag_pivot_pair(double (&d4)[4], double tol, bool& ok, int li,
+                                                int lg) {
+  constexpr int q = p + 1;
+  constexpr int gp = p & 3, ep = p >> 2, gq = q & 3, eq = q >> 2;
+  const double a = read_lane(d4[ep], p + 16 * gp);
+  const double b = read_lane(d4[eq], p + 16 * gq);  // D[p][q]
+  const double c = read_lane(d4[eq], q + 16 * gq);
+  const double det = fma(a, c, -b * b);
+  ok = ok && a > tol && det > tol * a;
+  const double idet = recip(det);
+  double zp = rows_bcast<gp>(d4[ep]);  // D[li][p]
+  double zq = rows_bcast<gq>(d4[eq]);  // D[li][q]
+  double wp[4], wq[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    wp[e] = row_bcast<p>(d4[e]);  // D[p][4 e + lg]
+    wq[e] = row_bcast<q>(d4[e]);  // D[q][4 e + lg]
+  }
+  if (li == p) {
+    zp = -1.0;
+    zq = 0.0;
+  }
+  if (li == q) {
+    zp = 0.0;
+    zq = -1.0;
+  }
+  // -(z_i B^{-1})
+  const double sp = -idet * fma(zp, c, -zq * b);
+  const double sq = -idet * fma(zq, a, -zp * b);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const bool cp = 4 * e + lg == p, cq = 4 * e + lg == q;
+    const double x = (li == p || li == q || cp || cq) ? 0.0 : d4[e];
+    const double up = cp ? -1.0 : (cq ? 0.0 : wp[e]);
+    const double uq = cq ? -1.0 : (cp ? 0.0 : wq[e]);
+    d4[e] = fma(sp, up, fma(sq, uq, x));
+  }
+}
+
+// All pivots p < nbv of the block: pairs while both are pivots, then one.
 template <int p>
 __device__ __forceinline__ void diag_pivots(double (&d4)[4], int nbv, double tol, bool& ok, int li,
                                             int lg) {
   if constexpr (p < 16) {
-    diag_pivot<p>(d4, nbv, tol, ok, li, lg);
-    diag_pivots<p + 1>(d4, nbv, tol, ok, li, lg);
+    if (p + 1 < nbv) {  // uniform
+      diag_pivot_pair<p>(d4, tol, ok, li, lg);
+      diag_pivots<p + 2>(d4, nbv, tol, ok, li, lg);
+    } else if (p < nbv) {
+      diag_pivot<p>(d4, nbv, tol, ok, li, lg);
+    }
   }
 }
 
@@ -310,7 +361,7 @@ struct SweepLds {
   double* dtout;  // 2 swept diagonal tiles handed back
   double* ysc;    // wave 0's scratch rows
   double* wmax;
-  int* diag_ok;
+  int* diag_ok;  // 2, by block parity
   int pan_stride;
 };
 
@@ -361,10 +412,10 @@ __device__ __forceinline__ bool sweep_pivot_role(const SweepLds& L, int npiv, in
         yp[li * LD + k] = k < nbv ? -d4[e] : 0.0;  // the columns in B hold Y
         dt[k * LD + li] = d4[e];
       }
-      if (lane == 0) *L.diag_ok = okb;
+      if (lane == 0) L.diag_ok[b & 1] = okb;
     }
     __syncthreads();
-    if (b < nblk) ok = *L.diag_ok != 0;
+    if (b < nblk) ok = L.diag_ok[b & 1] != 0;
     if (!ok) break;
   }
   return ok;
@@ -482,7 +533,7 @@ __device__ __forceinline__ bool sweep_update_role(const SweepLds& L, const doubl
       });
     }
     __syncthreads();
-    if (t - 1 < nblk) ok = *L.diag_ok != 0;
+    if (t - 1 < nblk) ok = L.diag_ok[(t - 1) & 1] != 0;
     if (!ok) break;
   }
 
@@ -523,9 +574,9 @@ __device__ __forceinline__ void sweep_matrix(
   __shared__ __attribute__((aligned(16))) double ybufp[16 * R * LD];
   __shared__ __attribute__((aligned(16))) double tiles16[7 * TL];
   __shared__ double wmax[kSweepWaves];
-  __shared__ int diag_ok;
+  __shared__ int diag_ok[2];
   const SweepLds L{pan,           ybufw,          ybufp,    tiles16,  tiles16 + 2 * TL,
-                   tiles16 + 4 * TL, tiles16 + 6 * TL, wmax, &diag_ok, 16 * R * LD};
+                   tiles16 + 4 * TL, tiles16 + 6 * TL, wmax, diag_ok, 16 * R * LD};
   const int lane = threadIdx.x & (kWave - 1);
   // the wave index is uniform: readfirstlane lets each wave take its role
   // (and its tiles) as a scalar branch
@@ -871,18 +922,11 @@ hipError_t gram_typed(int m, int n, int K, const T* W, int64_t ldw, void* work, 
   const int dtype = sizeof(T) == 4 ? GNMPPI_F32 : GNMPPI_F64;
   const JacPlan pl = jacobian_plan(dtype, m, n, K, GNMPPI_JAC_LS);
   char* wk = static_cast<char*>(work);
-  hipError_t e;
-  if constexpr (sizeof(T) == 4) {
-    // the bf16 hi / lo planes of W for a BF16 sample contraction (also W only)
-    __bf16* hi = reinterpret_cast<__bf16*>(wk + pl.bf16_off);
-    e = launch_split_bf16(n, K, pl.kpad, W, ldw, hi, hi + static_cast<size_t>(n) * pl.kpad, st);
-    if (e != hipSuccess) return e;
-  }
   T* gpart = reinterpret_cast<T*>(wk + pl.gpart_off);
   const int64_t split_stride = static_cast<int64_t>(n) * pl.npad;
   ContractArgs<T> c{n, n, n, K, W, ldw, nullptr, nullptr, 0, W, ldw, pl.gsplit_len,
                     gpart, pl.npad, split_stride, pl.npad};
-  e = launch_contract(c, pl.gsplit, st);
+  hipError_t e = launch_contract(c, pl.gsplit, st);
   if (e != hipSuccess) return e;
   return gram_inverse_typed<T>(pl, n, K, W, ldw, wk, gpart, pl.gsplit, split_stride, 0, status, st);
 }
@@ -908,10 +952,8 @@ hipError_t jacobian_typed(int m, int n, int K, const T* R, int64_t ldr, const T*
         // S on the BF16 MFMA; G (LS) on the FP32 W-only contraction
         __bf16* hi = reinterpret_cast<__bf16*>(wk + pl.bf16_off);
         __bf16* lo = hi + static_cast<size_t>(n) * pl.kpad;
-        if (!ready) {  // with a ready G the planes came with it
-          e = launch_split_bf16(n, K, pl.kpad, W, ldw, hi, lo, st);
-          if (e != hipSuccess) return e;
-        }
+        e = launch_split_bf16(n, K, pl.kpad, W, ldw, hi, lo, st);
+        if (e != hipSuccess) return e;
         e = launch_contract_bf16(bf16_terms, m, n, K, R, ldr, r0, hi, lo, pl.kpad, pl.nsplit,
                                  pl.split_len, part, pl.npad, st);
         if (e != hipSuccess) return e;
