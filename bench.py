@@ -32,6 +32,11 @@ METRIC = "GN-MPPI iters/s, sample-steps/s, time-to-1e-3 cost gap vs plain (1 GPU
 PEAK = {"hbm_GBps": 8000.0, "fp32_TFLOPs": 157.3, "fp64_TFLOPs": 78.6, "bf16_TFLOPs": 2500.0}
 
 
+def progress(msg: str):
+    """One line per finished phase on stderr (the JSON result goes to stdout)."""
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+
 def flops_per_sample_step(prob) -> float:
     """Algorithmic FP operations of one f(x, u) evaluation with its residual
     and cost terms (counted from the model's definition, not the kernel).
@@ -135,6 +140,7 @@ def bench_sweep(args):
             e1.record()
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / 50
+            progress(f"sweep N={N} K={K}: {1e3 * ms:.1f} us/iteration")
             rows.append({"N": N, "K": K, "m": prob.m, "n": prob.n, "us_per_iter": 1e3 * ms,
                          "iters_per_s": 1e3 / ms,
                          "sample_steps_per_s": (K + 1 + st.n_alpha) * N / (ms * 1e-3)})
@@ -159,7 +165,7 @@ def bench_batched(args):
     st = wl.c2().settings
     L = st.n_alpha
     batch = BatchGNMPPI(inst, st, seed=1)
-    tune = autotune(batch, cache=None)
+    tune = autotune(batch, cache=None, log=progress)
     chunk = max(1, min(args.steps, 10))
     reps = max(1, args.steps // chunk)
     steps = reps * chunk
@@ -457,6 +463,7 @@ def main():
         "roofline": roofline,
     }
 
+    progress("timed region, per-call timing and roofline done")
     if not args.no_time_to_gap:
         with open(os.path.join(ROOT, "tests", "golden", "reference_optima.json")) as f:
             cstar = json.load(f)[w.name]["cstar"]
@@ -537,6 +544,7 @@ def main():
                                    "gap_threshold": 1e-3}
 
     if not args.no_cpu_baseline:
+        progress("timing the CPU oracle")
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(result))
 
