@@ -4,14 +4,14 @@
 //  * reduce_sym_kernel -- adds the k-split / row-chunk partial sums of a
 //      symmetric matrix (lower triangle) into a full symmetric double matrix,
 //      one block per row so that every partial load is in flight at once.
-//  * sweep_kernel<R> -- one workgroup of 16 x 16 threads sweeps an SPD matrix
-//      with the symmetric sweep operator (Gauss-Jordan elimination without
+//  * sweep_kernel<R> -- one workgroup of 4 waves sweeps an SPD matrix with
+//      the symmetric sweep operator (Gauss-Jordan elimination without
 //      pivoting; for an SPD matrix its pivots are the Cholesky pivots
-//      squared).  Thread (ty, tx) keeps the lower-triangle elements
-//      (ty + 16 r, tx + 16 c), c <= r < R, in registers.  Pivots go in
-//      blocks of 16: each wave sweeps the 16 x 16 pivot block on its own
-//      (cross-lane shuffles, no barrier), then one rank-16 update per block
-//      brings every element up to date -- three barriers per 16 pivots.
+//      squared).  The lower triangle lives in registers as 16 x 16 tiles of
+//      the f64 MFMA accumulator layout, whole tile rows per wave 1..3.
+//      Pivots go in blocks of 16: wave 0 sweeps each diagonal block in
+//      registers (two pivots per step), waves 1..3 apply the rank-16 update
+//      of the previous block on the MFMA meanwhile -- one barrier per block.
 //      Sweeping pivots 0..n-1 of [[H, g], [g^T, c]] leaves -H^{-1} in the
 //      leading block and H^{-1} g in the last row: the same kernel yields
 //      G^{-1} for the LS Jacobian and the GGN direction -(H^{-1} g) with no
