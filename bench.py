@@ -406,11 +406,11 @@ def main():
     Kc = solver.K
     Wv, Rv = solver.W[:, :Kc], solver.R[:, :Kc]
     for _ in range(3):
-        _lib.gnmppi_rollout(dp, solver.x0, solver.U, Wv, Kc, Rv, solver.C, solver.r0, solver.c0)
+        _lib.gnmppi_rollout(dp, solver.x0, solver.U, Wv, Kc, Rv, None, solver.r0, solver.c0)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(args.kernel_reps):
-        _lib.gnmppi_rollout(dp, solver.x0, solver.U, Wv, Kc, Rv, solver.C, solver.r0, solver.c0)
+        _lib.gnmppi_rollout(dp, solver.x0, solver.U, Wv, Kc, Rv, None, solver.r0, solver.c0)
     e1.record()
     torch.cuda.synchronize()
     rollout_us = e0.elapsed_time(e1) * 1e3 / args.kernel_reps

@@ -150,7 +150,8 @@ int gnmppi_sigma_points(int32_t dtype, int32_t n, double sigma, void *W,
  * Single shooting of K perturbed control sequences: column s = 0..K-1 uses
  * U + W[:, s] (W == NULL: every column uses U).  Writes the residual column
  * s to R[i*ldr + s] (i < m; R == NULL skips it: costs only) and
- * C[s] = 1/2 ||R[:, s]||^2.  If c0 != NULL the nominal sequence U itself is
+ * C[s] = 1/2 ||R[:, s]||^2 (C == NULL skips the costs: residuals only; R and
+ * C may not both be NULL when K > 0).  If c0 != NULL the nominal sequence U itself is
  * rolled out in the same launch: its cost goes to c0[0] and, if r0 != NULL,
  * its residual to r0[0..m-1] (contiguous).  K may be 0 when c0 != NULL.
  * x0: nx entries; U: n entries.  Errors: EINVAL for an unsupported model or

@@ -68,7 +68,7 @@ int gnmppi_rollout(const gnmppi_problem* p, const void* x0, const void* U, const
   if (!problem_ok(p) || !sizes_fit(p) || x0 == nullptr || U == nullptr) return GNMPPI_EINVAL;
   if (K < 0 || (K == 0 && c0 == nullptr)) return GNMPPI_EINVAL;
   if (K > 0) {
-    if (C == nullptr) return GNMPPI_EINVAL;
+    if (C == nullptr && R == nullptr) return GNMPPI_EINVAL;  // nothing wanted of the K columns
     if (W != nullptr && ldw < K) return GNMPPI_EINVAL;
     if (R != nullptr && ldr < K) return GNMPPI_EINVAL;
   }

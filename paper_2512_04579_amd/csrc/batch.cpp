@@ -182,7 +182,7 @@ Plan make_plan(int count, const gnmppi_batch_instance* in, const gnmppi_batch_se
     d.info = b.info;
     d.W = reinterpret_cast<float*>(take(sizeof(float) * d.n * d.ldw));
     d.R = reinterpret_cast<float*>(take(sizeof(float) * static_cast<size_t>(d.m) * d.ldr));
-    d.C = reinterpret_cast<float*>(take(sizeof(float) * d.K));
+    d.C = nullptr;  // the GN-MPPI step never reads the perturbed columns' costs
     d.r0 = reinterpret_cast<float*>(take(sizeof(float) * d.m));
     d.c0 = reinterpret_cast<float*>(take(sizeof(float)));
     d.J = reinterpret_cast<float*>(take(sizeof(float) * static_cast<size_t>(d.m) * d.n));

@@ -33,7 +33,7 @@ struct BatchInst {
   double* info;     // alpha*, C*, j* of the last line search
   float* W;
   float* R;
-  float* C;
+  float* C;       // null: the step needs no per-sample costs
   float* r0;
   float* c0;
   float* J;       // m x n

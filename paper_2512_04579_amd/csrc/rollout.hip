@@ -229,9 +229,10 @@ struct DirectSink {
 constexpr bool kDirectResidualStores = false;
 
 // Rolls out one sample on the G lanes of its group and returns the group's
-// cost 1/2 ||r||^2 (identical in every lane of the group).  All lanes of the
-// wave must call this together (the DPP shifts read neighbouring lanes).
-template <typename T, int G, class Ctrl, class Sink>
+// cost 1/2 ||r||^2 (identical in every lane of the group; 0 without COST,
+// which skips the cost terms).  All lanes of the wave must call this
+// together (the DPP shifts read neighbouring lanes).
+template <typename T, int G, bool COST, class Ctrl, class Sink>
 __device__ __forceinline__ T chain_rollout(const ChainDev<T>& cd, int N,
                                            const T* __restrict__ x0, const T* __restrict__ q,
                                            const T* __restrict__ r, const T* __restrict__ xref,
@@ -283,13 +284,17 @@ __device__ __forceinline__ T chain_rollout(const ChainDev<T>& cd, int N,
       const T e0 = wpx * (px - rpx), e1 = wpy * (py - rpy);
       const T e2 = wvx * (vx - rvx), e3 = wvy * (vy - rvy);
       const T f0 = wu0 * u0, f1 = wu1 * u1;
-      if (has_mass) cost += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
-      if (first) cost += f0 * f0 + f1 * f1;
+      if constexpr (COST) {
+        if (has_mass) cost += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
+        if (first) cost += f0 * f0 + f1 * f1;
+      }
       sink.step(k, i, has_mass, first, e0, e1, e2, e3, f0, f1);
     }
   }
+  if constexpr (COST) {
 #pragma unroll
-  for (int off = 1; off < G; off <<= 1) cost += __shfl_xor(cost, off, kWave);
+    for (int off = 1; off < G; off <<= 1) cost += __shfl_xor(cost, off, kWave);
+  }
   return T(0.5) * cost;
 }
 
@@ -322,6 +327,13 @@ __device__ __forceinline__ void rollout_chain_block(
   const int col = valid ? gcol : ncol - 1;  // idle groups repeat a valid column, never store
   const bool nominal = col == K;
   const int n = 2 * N;
+  // the cost terms only where a cost is stored (C, or the nominal's c0)
+  const bool want_cost =
+      C != nullptr || (c0 != nullptr && g * kSpb <= K && K < (g + 1) * kSpb);  // uniform
+  auto run = [&](const auto& ctrl, auto& sink) -> T {
+    return want_cost ? chain_rollout<T, G, true>(cd, N, x0, q, r, xref, ctrl, sink)
+                     : chain_rollout<T, G, false>(cd, N, x0, q, r, xref, ctrl, sink);
+  };
   if (stage_ctl) {
     // the block's controls U + W[:, s] in one coalesced burst: ctl[idx][sample]
     T* ctl = reinterpret_cast<T*>(ctl_raw);
@@ -338,18 +350,18 @@ __device__ __forceinline__ void rollout_chain_block(
     T c;
     if ((R != nullptr || r0 != nullptr) && kDirectResidualStores) {
       DirectSink<T> sink{R, ldr, r0, K, col, cd.M, valid};
-      c = chain_rollout<T, G>(cd, N, x0, q, r, xref, ctrl, sink);
+      c = run(ctrl, sink);
     } else if (R != nullptr || r0 != nullptr) {
       StagedSink<T, G, FL> sink{tile, R, ldr, r0, K, col0, cd.M, grp, N};
-      c = chain_rollout<T, G>(cd, N, x0, q, r, xref, ctrl, sink);
+      c = run(ctrl, sink);
     } else {
       NoSink sink;
-      c = chain_rollout<T, G>(cd, N, x0, q, r, xref, ctrl, sink);
+      c = run(ctrl, sink);
     }
     if (valid && (threadIdx.x & (G - 1)) == 0) {
       if (nominal)
         c0[0] = c;
-      else
+      else if (C != nullptr)
         C[col] = c;
     }
     return;
@@ -358,15 +370,15 @@ __device__ __forceinline__ void rollout_chain_block(
   T c;
   if (R != nullptr || r0 != nullptr) {
     StagedSink<T, G, FL> sink{tile, R, ldr, r0, K, g * kSpb, cd.M, grp, N};
-    c = chain_rollout<T, G>(cd, N, x0, q, r, xref, ctrl, sink);
+    c = run(ctrl, sink);
   } else {
     NoSink sink;
-    c = chain_rollout<T, G>(cd, N, x0, q, r, xref, ctrl, sink);
+    c = run(ctrl, sink);
   }
   if (valid && (threadIdx.x & (G - 1)) == 0) {
     if (nominal)
       c0[0] = c;
-    else
+    else if (C != nullptr)
       C[col] = c;
   }
 }
@@ -467,7 +479,7 @@ __global__ void __launch_bounds__(256) rollout_di_kernel(
     c = di_rollout<T, D, false>(N, dt, x0, q, r, xref, ctrl, nullptr, 0, 0, false);
   if (nominal)
     c0[0] = c;
-  else
+  else if (C != nullptr)
     C[col] = c;
 }
 
@@ -529,11 +541,11 @@ __device__ __forceinline__ void line_search_chain_block(
     __syncthreads();
     CtrlLineStaged<T> ctrl{Us, dUs, alpha[jj]};
     NoSink sink;
-    c = chain_rollout<T, G>(cd, N, x0, q, r, xref, ctrl, sink);
+    c = chain_rollout<T, G, true>(cd, N, x0, q, r, xref, ctrl, sink);
   } else {
     CtrlLine<T> ctrl{U, dU, alpha[jj]};
     NoSink sink;
-    c = chain_rollout<T, G>(cd, N, x0, q, r, xref, ctrl, sink);
+    c = chain_rollout<T, G, true>(cd, N, x0, q, r, xref, ctrl, sink);
   }
   if (j < L && (threadIdx.x & (G - 1)) == 0) costs[j] = c;
   line_select_and_apply(costs, L, n, U, dU, alpha, Cout, info, &jstar);

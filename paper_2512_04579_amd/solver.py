@@ -131,7 +131,8 @@ class GNMPPI:
             sampled = torch.cuda.Event()
             sampled.record()
         tick.next("rollout")
-        _lib.gnmppi_rollout(self.p, self.x0, self.U, W, K, self.R[:, :K], self.C, self.r0, self.c0)
+        # residuals and the nominal cost only: the step never reads C
+        _lib.gnmppi_rollout(self.p, self.x0, self.U, W, K, self.R[:, :K], None, self.r0, self.c0)
         if self.overlap:
             # enqueued after the rollout so that a captured graph keeps the
             # rollout on the sampling queue and forks only the W-only work

@@ -89,13 +89,13 @@ def test_rollout_rejects_bad_problems(kw):
 def test_rollout_rejects_bad_sizes():
     lib = _lib.load()
     p = _problem()
-    args = lambda K, ldw, ldr, C=0x50, c0=None, r0=None: (  # noqa: E731
-        ctypes.byref(p), 0x10, 0x20, 0x30, ldw, K, 0x40, ldr, C, r0, c0, None)
+    args = lambda K, ldw, ldr, C=0x50, c0=None, r0=None, R=0x40: (  # noqa: E731
+        ctypes.byref(p), 0x10, 0x20, 0x30, ldw, K, R, ldr, C, r0, c0, None)
     assert lib.gnmppi_rollout(*args(4096, 4095, 4096)) == _lib.EINVAL   # ldw < K
     assert lib.gnmppi_rollout(*args(4096, 4096, 100)) == _lib.EINVAL    # ldr < K
     assert lib.gnmppi_rollout(*args(-1, 4096, 4096)) == _lib.EINVAL
     assert lib.gnmppi_rollout(*args(0, 0, 0)) == _lib.EINVAL            # nothing to roll out
-    assert lib.gnmppi_rollout(*args(8, 8, 8, C=None)) == _lib.EINVAL
+    assert lib.gnmppi_rollout(*args(8, 8, 8, C=None, R=None)) == _lib.EINVAL  # neither R nor C
     assert lib.gnmppi_rollout(*args(8, 8, 8, r0=0x60)) == _lib.EINVAL   # r0 without c0
 
 

@@ -112,6 +112,15 @@ def test_rollout_matches_oracle(name):
     assert_parity(host(r0d), R_ref[:, 0], dtype, "r0")
     assert_parity(host(c0d), C_ref[:1], dtype, "c0")
     np.testing.assert_array_equal(host(C2), host(Cd))
+    # residuals-only launch (no C, as the GN-MPPI step calls it): the same R,
+    # r0 and c0 bit for bit
+    R3 = padded(np.zeros((prob.m, K)), dtype)
+    r03, c03 = to_dev(np.zeros(prob.m), dtype), to_dev(np.zeros(1), dtype)
+    _lib.gnmppi_rollout(dp, x0d, Ud, Wd, K, R3, None, r03, c03)
+    _sync()
+    np.testing.assert_array_equal(host(R3), host(Rd))
+    np.testing.assert_array_equal(host(r03), host(r0d))
+    np.testing.assert_array_equal(host(c03), host(c0d))
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
