@@ -889,8 +889,7 @@ JacPlan jacobian_plan(int dtype, int m, int n, int K, int method) {
   split_plan(n, K, step, kw, p.gsplit, p.gsplit_len);
   p.gpart_off = p.s_off + align_up(static_cast<size_t>(m) * p.npad * esz);
   p.kpad = (K + 31) / 32 * 32;
-  p.bf16_off = p.gpart_off + align_up(static_cast<size_t>(p.gsplit) * n * p.npad * esz);
-  p.total = p.bf16_off + (dtype == GNMPPI_F32 ? align_up(static_cast<size_t>(2) * n * p.kpad * 2) : 0);
+  p.total = p.gpart_off + align_up(static_cast<size_t>(p.gsplit) * n * p.npad * esz);
   if (method & (GNMPPI_JAC_BF16 | GNMPPI_JAC_BF16X3)) {
     p.rows = m;  // G is formed by the FP32 W-only contraction
     bf16_split_plan(m, K, p.nsplit, p.split_len);
@@ -949,13 +948,10 @@ hipError_t jacobian_typed(int m, int n, int K, const T* R, int64_t ldr, const T*
   if (!apply_only) {
     if constexpr (sizeof(T) == 4) {
       if (bf16_terms) {
-        // S on the BF16 MFMA; G (LS) on the FP32 W-only contraction
-        __bf16* hi = reinterpret_cast<__bf16*>(wk + pl.bf16_off);
-        __bf16* lo = hi + static_cast<size_t>(n) * pl.kpad;
-        e = launch_split_bf16(n, K, pl.kpad, W, ldw, hi, lo, st);
-        if (e != hipSuccess) return e;
-        e = launch_contract_bf16(bf16_terms, m, n, K, R, ldr, r0, hi, lo, pl.kpad, pl.nsplit,
-                                 pl.split_len, part, pl.npad, st);
+        // S on the BF16 MFMA (W split on the fly); G (LS) on the FP32 W-only
+        // contraction
+        e = launch_contract_bf16(bf16_terms, m, n, K, R, ldr, r0, W, ldw, pl.nsplit, pl.split_len,
+                                 part, pl.npad, st);
         if (e != hipSuccess) return e;
         if (base == GNMPPI_JAC_LS && !ready) {
           e = gram_typed<T>(m, n, K, W, ldw, work, status, st);

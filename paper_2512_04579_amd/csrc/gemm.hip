@@ -22,6 +22,8 @@
 // (measured with a one-wave probe).  A lane that loads k-values kl..kl+V-1 feeds
 // them to V consecutive MFMAs; the k-permutation this induces is the same
 // for A and B, so the sum is unchanged.
+#include <type_traits>
+
 #include "batch.hpp"
 #include "common.hpp"
 #include "launch.hpp"
@@ -292,7 +294,8 @@ using bf16x8 = __bf16 __attribute__((ext_vector_type(8)));
 using f32x4 = float __attribute__((ext_vector_type(4)));
 constexpr int kBf16Step = 32;
 
-// W (n x K, ldw) -> hi and lo bf16 planes (n x kpad), zero beyond K.
+// W (n x K, ldw) -> hi and lo bf16 planes (n x kpad), zero beyond K (the
+// batched form's planes; a single launch splits W inside the contraction).
 __device__ __forceinline__ void split_bf16_block(int K, int kpad, const float* __restrict__ W,
                                                  int64_t ldw, __bf16* __restrict__ hi,
                                                  __bf16* __restrict__ lo, int bx, int row) {
@@ -302,12 +305,6 @@ __device__ __forceinline__ void split_bf16_block(int K, int kpad, const float* _
   const __bf16 h = static_cast<__bf16>(v);
   hi[static_cast<int64_t>(row) * kpad + k] = h;
   lo[static_cast<int64_t>(row) * kpad + k] = static_cast<__bf16>(v - static_cast<float>(h));
-}
-
-__global__ void __launch_bounds__(256) split_bf16_kernel(int K, int kpad, const float* __restrict__ W,
-                                                         int64_t ldw, __bf16* __restrict__ hi,
-                                                         __bf16* __restrict__ lo) {
-  split_bf16_block(K, kpad, W, ldw, hi, lo, blockIdx.x, blockIdx.y);
 }
 
 // Batched: tile = row * ceil(kpad / 256) + k-chunk.
@@ -330,15 +327,26 @@ __global__ void __launch_bounds__(256) batch_split_bf16_kernel(const BatchInst* 
 // streams from HBM into registers two steps ahead (kept raw until its step, so
 // no load is waited on early), is shifted by r0 and converted to bf16 (and
 // split into hi + lo) in registers.  One barrier per step.
-template <int TERMS, int NT, int TM, bool VEC>
+//
+// WF32: B comes from the FP32 W itself (Wf, leading dimension ldw; Bh, Bl
+// unused) and is rounded (TERMS = 1) or split into hi + lo (TERMS = 3) on
+// its way into LDS -- the same arithmetic as the split pass, without it.
+// Each thread then loads 8-value pieces of W rows (two 16-byte loads when
+// wvec: ldw % 4 == 0 and Wf 16-byte aligned) and writes both planes.
+using f32x8 = float __attribute__((ext_vector_type(8)));
+template <int TERMS, int NT, int TM, bool VEC, bool WF32 = false>
 __device__ __forceinline__ void contract_bf16_block(
     int m, int n, int K, const float* __restrict__ R, int64_t ldr, const float* __restrict__ r0,
     const __bf16* __restrict__ Bh, const __bf16* __restrict__ Bl, int kpad, int split_len,
-    float* __restrict__ part, int npad, int bx, int by) {
+    float* __restrict__ part, int npad, int bx, int by, const float* __restrict__ Wf = nullptr,
+    int64_t ldw = 0, bool wvec = false) {
   constexpr int PLANES = TERMS == 3 ? 2 : 1;
   constexpr int NCOL = 16 * NT;
-  constexpr int CHUNKS = PLANES * NCOL * (kBf16Step / 8);  // 16-byte pieces per stage
+  // pieces per stage: 16-byte bf16 pieces of each plane, or 8-value FP32
+  // pieces that yield both planes
+  constexpr int CHUNKS = (WF32 ? 1 : PLANES) * NCOL * (kBf16Step / 8);
   constexpr int PER_THREAD = (CHUNKS + 255) / 256;
+  using BReg = std::conditional_t<WF32, f32x8, bf16x8>;
   __shared__ bf16x8 stage[2][PLANES][kBf16Step / 8][NCOL];
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1), wave = tid / kWave;
@@ -359,6 +367,7 @@ __device__ __forceinline__ void contract_bf16_block(
   // the B pieces this thread copies: piece c -> (plane, column, k-group),
   // k-group fastest so that 8 neighbouring threads read one 128-byte run
   const __bf16* bsrc[PER_THREAD];
+  const float* wsrc[PER_THREAD];
   bool bvalid[PER_THREAD];
 #pragma unroll
   for (int i = 0; i < PER_THREAD; ++i) {
@@ -366,21 +375,58 @@ __device__ __forceinline__ void contract_bf16_block(
     const int kg = c % (kBf16Step / 8), col = (c / (kBf16Step / 8)) % NCOL;
     const int pl = c / (NCOL * (kBf16Step / 8));
     bvalid[i] = c < CHUNKS && col < n;
-    bsrc[i] = (pl == 0 ? Bh : Bl) + static_cast<int64_t>(col < n ? col : 0) * kpad + 8 * kg;
+    const int64_t cc = col < n ? col : 0;
+    if constexpr (WF32)
+      wsrc[i] = Wf + cc * ldw + 8 * kg;
+    else
+      bsrc[i] = (pl == 0 ? Bh : Bl) + cc * kpad + 8 * kg;
   }
-  auto load_b = [&](int k0, bf16x8 (&reg)[PER_THREAD]) {
+  auto load_b = [&](int k0, BReg (&reg)[PER_THREAD]) {
 #pragma unroll
-    for (int i = 0; i < PER_THREAD; ++i)
-      reg[i] = bvalid[i] ? *reinterpret_cast<const bf16x8*>(bsrc[i] + k0) : bf16x8{};
+    for (int i = 0; i < PER_THREAD; ++i) {
+      if constexpr (WF32) {
+        // 8 values of W at k = k0 + 8 kg + e, zero at k >= K
+        const int kk = k0 + 8 * ((tid + 256 * i) % (kBf16Step / 8));
+        f32x8 v = f32x8{0, 0, 0, 0, 0, 0, 0, 0};
+        if (bvalid[i]) {
+          if (wvec && kk + 8 <= K) {
+            const f32x4 x0 = *reinterpret_cast<const f32x4*>(wsrc[i] + k0);
+            const f32x4 x1 = *reinterpret_cast<const f32x4*>(wsrc[i] + k0 + 4);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              v[e] = x0[e];
+              v[4 + e] = x1[e];
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = kk + e < K ? wsrc[i][k0 + e] : 0.0f;
+          }
+        }
+        reg[i] = v;
+      } else {
+        reg[i] = bvalid[i] ? *reinterpret_cast<const bf16x8*>(bsrc[i] + k0) : bf16x8{};
+      }
+    }
   };
-  auto store_b = [&](int buf, const bf16x8 (&reg)[PER_THREAD]) {
+  auto store_b = [&](int buf, const BReg (&reg)[PER_THREAD]) {
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int c = tid + 256 * i;
       if (c < CHUNKS) {
         const int kg = c % (kBf16Step / 8), col = (c / (kBf16Step / 8)) % NCOL;
-        const int pl = c / (NCOL * (kBf16Step / 8));
-        stage[buf][pl][kg][col] = reg[i];
+        if constexpr (WF32) {
+          bf16x8 h, l;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            h[e] = static_cast<__bf16>(reg[i][e]);
+            l[e] = static_cast<__bf16>(reg[i][e] - static_cast<float>(h[e]));
+          }
+          stage[buf][0][kg][col] = h;
+          if constexpr (TERMS == 3) stage[buf][PLANES - 1][kg][col] = l;
+        } else {
+          const int pl = c / (NCOL * (kBf16Step / 8));
+          stage[buf][pl][kg][col] = reg[i];
+        }
       }
     }
   };
@@ -416,7 +462,7 @@ __device__ __forceinline__ void contract_bf16_block(
 
   if (nstep > 0) {
     // A two steps ahead (HBM latency), B one step ahead (L2 -> LDS)
-    bf16x8 breg[PER_THREAD];
+    BReg breg[PER_THREAD];
     float a0[TM][8], a1[TM][8];
     load_b(kbeg, breg);
     load_a(kbeg, a0);
@@ -481,10 +527,10 @@ __device__ __forceinline__ void contract_bf16_block(
 template <int TERMS, int NT, int TM, bool VEC>
 __global__ void __launch_bounds__(256) contract_bf16_kernel(
     int m, int n, int K, const float* __restrict__ R, int64_t ldr, const float* __restrict__ r0,
-    const __bf16* __restrict__ Bh, const __bf16* __restrict__ Bl, int kpad, int split_len,
-    float* __restrict__ part, int npad) {
-  contract_bf16_block<TERMS, NT, TM, VEC>(m, n, K, R, ldr, r0, Bh, Bl, kpad, split_len, part, npad,
-                                          blockIdx.x, blockIdx.y);
+    const float* __restrict__ Wf, int64_t ldw, bool wvec, int split_len, float* __restrict__ part,
+    int npad) {
+  contract_bf16_block<TERMS, NT, TM, VEC, true>(m, n, K, R, ldr, r0, nullptr, nullptr, 0, split_len,
+                                                part, npad, blockIdx.x, blockIdx.y, Wf, ldw, wvec);
 }
 
 // Batched S = (R - r0 1^T) W^T partials, BF16x3; tile = split * row_blocks + row block.
@@ -504,12 +550,12 @@ __global__ void __launch_bounds__(256) batch_contract_bf16_kernel(const BatchIns
 
 template <int TERMS, bool VEC>
 hipError_t bf16_dispatch(int nt, dim3 grid, hipStream_t st, int m, int n, int K, const float* R,
-                         int64_t ldr, const float* r0, const __bf16* Bh, const __bf16* Bl, int kpad,
+                         int64_t ldr, const float* r0, const float* W, int64_t ldw, bool wvec,
                          int split_len, float* part, int npad) {
 #define GNM_BF_CASE(NT)                                                                        \
   case NT:                                                                                     \
     hipLaunchKernelGGL((contract_bf16_kernel<TERMS, NT, kBf16RowTiles, VEC>), grid, dim3(256), 0, \
-                       st, m, n, K, R, ldr, r0, Bh, Bl, kpad, split_len, part, npad);          \
+                       st, m, n, K, R, ldr, r0, W, ldw, wvec, split_len, part, npad);          \
     break;
   switch (nt) {
     GNM_BF_CASE(1) GNM_BF_CASE(2) GNM_BF_CASE(3) GNM_BF_CASE(4) GNM_BF_CASE(5) GNM_BF_CASE(6)
@@ -586,27 +632,22 @@ hipError_t launch_batch_contract_bf16(int nt, const BatchInst* inst, const Batch
   return hipGetLastError();
 }
 
-hipError_t launch_split_bf16(int n, int K, int kpad, const float* W, int64_t ldw, __bf16* hi,
-                             __bf16* lo, hipStream_t st) {
-  hipLaunchKernelGGL(split_bf16_kernel, dim3((kpad + 255) / 256, n), dim3(256), 0, st, K, kpad, W,
-                     ldw, hi, lo);
-  return hipGetLastError();
-}
 
 hipError_t launch_contract_bf16(int terms, int m, int n, int K, const float* R, int64_t ldr,
-                                const float* r0, const __bf16* Bh, const __bf16* Bl, int kpad,
-                                int nsplit, int split_len, float* part, int npad, hipStream_t st) {
+                                const float* r0, const float* W, int64_t ldw, int nsplit,
+                                int split_len, float* part, int npad, hipStream_t st) {
   dim3 grid((m + 64 * kBf16RowTiles - 1) / (64 * kBf16RowTiles), nsplit);
   const int nt = (n + 15) / 16;
   const bool vec = (ldr % 4 == 0) && (reinterpret_cast<uintptr_t>(R) % 16 == 0);
+  const bool wvec = (ldw % 4 == 0) && (reinterpret_cast<uintptr_t>(W) % 16 == 0);
   if (terms == 3)
-    return vec ? bf16_dispatch<3, true>(nt, grid, st, m, n, K, R, ldr, r0, Bh, Bl, kpad, split_len,
+    return vec ? bf16_dispatch<3, true>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, wvec, split_len,
                                         part, npad)
-               : bf16_dispatch<3, false>(nt, grid, st, m, n, K, R, ldr, r0, Bh, Bl, kpad, split_len,
-                                         part, npad);
-  return vec ? bf16_dispatch<1, true>(nt, grid, st, m, n, K, R, ldr, r0, Bh, Bl, kpad, split_len,
+               : bf16_dispatch<3, false>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, wvec,
+                                         split_len, part, npad);
+  return vec ? bf16_dispatch<1, true>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, wvec, split_len,
                                       part, npad)
-             : bf16_dispatch<1, false>(nt, grid, st, m, n, K, R, ldr, r0, Bh, Bl, kpad, split_len,
+             : bf16_dispatch<1, false>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, wvec, split_len,
                                        part, npad);
 }
 

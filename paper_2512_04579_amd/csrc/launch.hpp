@@ -60,13 +60,11 @@ constexpr int kBf16RowTiles = 1;
 hipError_t launch_contract(const ContractArgs<float>& a, int nsplit, hipStream_t st);
 hipError_t launch_contract(const ContractArgs<double>& a, int nsplit, hipStream_t st);
 
-// BF16 MFMA contraction S = (R - r0 1^T) W^T (terms = 1 or 3), W given as
-// hi / lo bf16 planes n x kpad produced by launch_split_bf16.
-hipError_t launch_split_bf16(int n, int K, int kpad, const float* W, int64_t ldw, __bf16* hi,
-                             __bf16* lo, hipStream_t st);
+// BF16 MFMA contraction S = (R - r0 1^T) W^T (terms = 1 or 3); it reads the
+// FP32 W and rounds / splits it on its way into LDS.
 hipError_t launch_contract_bf16(int terms, int m, int n, int K, const float* R, int64_t ldr,
-                                const float* r0, const __bf16* Bh, const __bf16* Bl, int kpad,
-                                int nsplit, int split_len, float* part, int npad, hipStream_t st);
+                                const float* r0, const float* W, int64_t ldw, int nsplit,
+                                int split_len, float* part, int npad, hipStream_t st);
 
 // Jacobian reconstruction; `work` holds the GEMM partials, G, G^{-1} and S.
 struct JacPlan {
@@ -83,7 +81,6 @@ struct JacPlan {
   int gsplit_len;
   size_t gpart_off;  // byte offset of its partial sums (gsplit x n x npad)
   int kpad;          // K rounded up to the BF16 MFMA k-step
-  size_t bf16_off;   // byte offset of the hi / lo bf16 planes of W (2 x n x kpad)
   size_t total;      // workspace bytes
 };
 JacPlan jacobian_plan(int dtype, int m, int n, int K, int method);
