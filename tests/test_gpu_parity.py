@@ -416,6 +416,31 @@ def test_ggn_step_reports_singular_normal_matrix():
     np.testing.assert_array_equal(dU, np.zeros(6))
 
 
+@pytest.mark.parametrize("dup,src", [(17, 16), (25, 3), (26, 3), (39, 38), (32, 0)])
+def test_ggn_step_detects_a_late_zero_pivot(dup, src):
+    # column dup repeats column src: the Schur complement at pivot dup is zero
+    # (dup odd: the second pivot of a 2 x 2 step; even: the first; 32: the
+    # first pivot of block 2, reached after two pipelined blocks)
+    rng = np.random.default_rng(dup)
+    J = rng.standard_normal((120, 40))
+    J[:, dup] = J[:, src]
+    dU, st = _run_ggn(J, rng.standard_normal(120), 0.0, "f64")
+    assert st == _lib.ENOTPD
+    np.testing.assert_array_equal(dU, np.zeros(40))
+
+
+@pytest.mark.parametrize("dup", [5, 20, 37])
+def test_jacobian_detects_a_late_zero_pivot_of_g(dup):
+    # W row dup repeats row 2: G = W W^T is singular from pivot dup on
+    rng = np.random.default_rng(dup)
+    n, K = 40, 256
+    W = rng.standard_normal((n, K))
+    W[dup] = W[2]
+    R = rng.standard_normal((90, K + 1))
+    _, st = _run_jacobian(R, W, "f64")
+    assert st == _lib.ERANK
+
+
 # ---------------------------------------------------------------------------
 # a6: line search + apply
 # ---------------------------------------------------------------------------
