@@ -619,7 +619,7 @@ __global__ void __launch_bounds__(kSweepTD * kSweepTD) batch_sweep_kernel(
   }
 }
 
-// One workgroup of 16 x 16 threads; R = ceil(P / 16) <= 13 for P <= 208.
+// One workgroup of 4 waves; R = ceil(P / 16) <= 13 for P <= 208.
 template <typename TO>
 hipError_t launch_sweep(int P, int npiv, int mode, const double* M, TO* inv_out, int64_t ldo,
                         TO* dir_out, int32_t* status, int fail_code, hipStream_t st) {
