@@ -31,7 +31,7 @@ CACHE = os.path.join(os.path.expanduser("~"), ".cache", "gnmppi", "batch_autotun
 # Candidate values of each tuning field (0 = the library's default).
 TUNING_SPACE = {
     "rollout_blocks_per_cu": (16, 32, 64),
-    "contract_blocks_per_cu": (2, 3, 4),
+    "contract_blocks_per_cu": (16, 32, 64),
     "contract_ksplit": (1, 2),
     "small_blocks_per_cu": (8, 16, 32),
 }

@@ -61,7 +61,7 @@ bool settings_ok(const gnmppi_batch_settings* s) {
 
 gnmppi_batch_tuning effective(const gnmppi_batch_tuning* t) {
   // defaults: the autotuner's pick for 1024 uneven chain instances
-  gnmppi_batch_tuning d{32, 3, 1, 16};
+  gnmppi_batch_tuning d{64, 16, 1, 32};
   if (t) {
     if (t->rollout_blocks_per_cu > 0) d.rollout_blocks_per_cu = t->rollout_blocks_per_cu;
     if (t->contract_blocks_per_cu > 0) d.contract_blocks_per_cu = t->contract_blocks_per_cu;

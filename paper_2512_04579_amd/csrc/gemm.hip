@@ -540,8 +540,8 @@ __global__ void __launch_bounds__(256) batch_contract_bf16_kernel(const BatchIns
   for (int w = blockIdx.x; w < L.count; w += gridDim.x) {
     const BatchItem it = L.items[w];
     const BatchInst& b = inst[it.inst];
-    const int rb = (b.m + 64 * kBf16RowTiles - 1) / (64 * kBf16RowTiles);
-    contract_bf16_block<3, NT, kBf16RowTiles, true>(b.m, b.n, b.K, b.R, b.ldr, b.r0, b.Wh, b.Wl,
+    const int rb = (b.m + 64 * kBatchBf16RowTiles - 1) / (64 * kBatchBf16RowTiles);
+    contract_bf16_block<3, NT, kBatchBf16RowTiles, true>(b.m, b.n, b.K, b.R, b.ldr, b.r0, b.Wh, b.Wl,
                                                     b.kpad, b.split_len, b.part, b.npad,
                                                     it.tile % rb, it.tile / rb);
     __syncthreads();
@@ -585,7 +585,9 @@ hipError_t launch_contract(const ContractArgs<double>& a, int nsplit, hipStream_
 int batch_contract_row_blocks(int rows, int mode) {
   return mode == 0 ? (rows + 15) / 16 : (rows + 63) / 64;
 }
-int batch_bf16_row_blocks(int m) { return (m + 64 * kBf16RowTiles - 1) / (64 * kBf16RowTiles); }
+int batch_bf16_row_blocks(int m) {
+  return (m + 64 * kBatchBf16RowTiles - 1) / (64 * kBatchBf16RowTiles);
+}
 
 hipError_t launch_batch_contract(int mode, int nt, const BatchInst* inst, const BatchLaunch& L,
                                  hipStream_t st) {

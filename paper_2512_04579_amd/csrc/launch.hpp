@@ -57,6 +57,9 @@ int contract_kw(size_t elem_size, int ncol);
 // launch_contract_bf16: 16-row MFMA tiles per wave (a block covers 64 times
 // as many rows) and the planner's target for its blocks per k-slice.
 constexpr int kBf16RowTiles = 1;
+// The batched contraction (throughput-bound, plenty of blocks) takes two
+// row tiles per wave: each staged B fragment then feeds twice the MFMAs.
+constexpr int kBatchBf16RowTiles = 2;
 hipError_t launch_contract(const ContractArgs<float>& a, int nsplit, hipStream_t st);
 hipError_t launch_contract(const ContractArgs<double>& a, int nsplit, hipStream_t st);
 
