@@ -131,10 +131,14 @@ struct NoSink {
 };
 
 // StagedSink collects the residual rows of the block's samples in an LDS
-// tile (F steps x rows x samples, double-buffered) and every F steps (and at
-// the last step) stores each row as one contiguous segment of the
-// sample-fastest R (or into r0 for the nominal column).  One barrier per F
-// steps; all threads of the block must call it.
+// tile (double-buffered; step j of a flush occupies rows j (4 M + 2) ..,
+// so the tile's rows are consecutive rows of R) and every F steps (and at
+// the last step) stores them as contiguous row segments of the
+// sample-fastest R (or into r0 for the nominal column), four samples per
+// store.  Column K (the nominal) and the columns left of it in a partial
+// last chunk go one row per thread; the threads that store column K also
+// sum its squares, so the nominal cost needs no cost terms in the rollout
+// itself.  One barrier per F steps; all threads of the block must call it.
 template <typename T, int G, int F>
 struct StagedSink {
   static constexpr int kSpb = kBlock / G;        // samples per block
@@ -142,15 +146,21 @@ struct StagedSink {
   // row stride kSpb + 1: the G lanes of a sample write rows 2i of one column,
   // which a stride of kSpb would put in a single LDS bank
   static constexpr int kLd = kSpb + 1;
-  T (*tile)[F][kRows][kLd];                      // [2][F][kRows][kLd] in LDS
+  static constexpr int kVec = 4;                 // samples per vector store
+  static constexpr int kChunks = kSpb / kVec;    // vector stores per row
+  static_assert(kSpb % kVec == 0 && kBlock % kChunks == 0, "chunking of a row");
+  T (*tile)[F * kRows][kLd];                     // [2][F kRows][kLd] in LDS
   T* R;
   int64_t ldr;
   T* r0;
   int K, col0, M, grp, N;
+  bool vec;    // rows of R start 4-element aligned (uniform)
+  T csum = 0;  // this thread's share of ||r||^2 of column K (the nominal)
   __device__ __forceinline__ void step(int k, int i, bool has_mass, bool first, T e0, T e1, T e2,
                                        T e3, T f0, T f1) {
+    const int rows = 4 * M + 2;
     const int buf = (k / F) & 1, j = k % F;
-    T (*t)[kLd] = tile[buf][j];
+    T (*t)[kLd] = tile[buf] + j * rows;
     if (has_mass) {
       t[2 * i][grp] = e0;
       t[2 * i + 1][grp] = e1;
@@ -163,17 +173,45 @@ struct StagedSink {
     }
     if (j != F - 1 && k != N - 1) return;  // uniform: flush every F steps and at the end
     __syncthreads();
-    const int rows = 4 * M + 2;
-    for (int jj = 0; jj <= j; ++jj) {
-      const int64_t base = static_cast<int64_t>(k - j + jj) * rows;
-      for (int idx = threadIdx.x; idx < rows * kSpb; idx += kBlock) {
-        const int row = idx / kSpb, s = idx % kSpb;
-        const int c = col0 + s;
-        const T v = tile[buf][jj][row][s];
+    // tile row fr is row (k - j) rows + fr of R
+    const int64_t base = static_cast<int64_t>(k - j) * rows;
+    const int nfr = (j + 1) * rows;
+    if (vec) {
+      // whole 4-sample chunks left of column K: one vector store each
+      using V = T __attribute__((ext_vector_type(kVec)));
+      const int nvec = min(kChunks, max(0, (K - col0) / kVec));  // uniform
+      for (int idx = threadIdx.x; idx < nfr * kChunks; idx += kBlock) {
+        const int fr = idx / kChunks, ch = idx % kChunks, sv = ch * kVec;
+        if (ch < nvec)
+          *reinterpret_cast<V*>(R + (base + fr) * ldr + col0 + sv) =
+              V{tile[buf][fr][sv], tile[buf][fr][sv + 1], tile[buf][fr][sv + 2],
+                tile[buf][fr][sv + 3]};
+      }
+      // the block that holds column K: its last R columns and the nominal,
+      // one row per thread (the bounds are uniform, so the stores need no
+      // divergent branches)
+      const int ctail = col0 + nvec * kVec, cend = min(col0 + kSpb, K);
+      const bool nom = col0 <= K && K < col0 + kSpb;
+      if (ctail < cend || nom) {
+        for (int fr = threadIdx.x; fr < nfr; fr += kBlock) {
+          for (int c = ctail; c < cend; ++c) R[(base + fr) * ldr + c] = tile[buf][fr][c - col0];
+          if (nom) {
+            const T v = tile[buf][fr][K - col0];
+            if (r0) r0[base + fr] = v;
+            csum += v * v;
+          }
+        }
+      }
+    } else {
+      for (int idx = threadIdx.x; idx < nfr * kSpb; idx += kBlock) {
+        const int fr = idx / kSpb, sc = idx % kSpb;
+        const int c = col0 + sc;
+        const T v = tile[buf][fr][sc];
         if (c < K) {
-          if (R) R[(base + row) * ldr + c] = v;
-        } else if (c == K && r0) {
-          r0[base + row] = v;
+          if (R) R[(base + fr) * ldr + c] = v;
+        } else if (c == K) {
+          if (r0) r0[base + fr] = v;
+          csum += v * v;
         }
       }
     }
@@ -187,46 +225,6 @@ constexpr int staged_flush_steps() {
   constexpr int f = 24576 / per_step;
   return f < 1 ? 1 : (f > 8 ? 8 : f);
 }
-
-// DirectSink stores each lane's residual entries straight to R: for a fixed
-// row the sample groups of a block write consecutive columns, which meet in
-// L2 before they go to HBM.  No LDS and no barrier per step.
-template <typename T>
-struct DirectSink {
-  T* R;
-  int64_t ldr;
-  T* r0;
-  int K, col, M;
-  bool valid;
-  __device__ __forceinline__ void step(int k, int i, bool has_mass, bool first, T e0, T e1, T e2,
-                                       T e3, T f0, T f1) {
-    if (!valid) return;
-    const int64_t base = static_cast<int64_t>(k) * (4 * M + 2);
-    T* p;
-    int64_t ld;
-    if (col < K) {
-      p = R + col;
-      ld = ldr;
-    } else {
-      if (r0 == nullptr) return;
-      p = r0;
-      ld = 1;
-    }
-    if (has_mass) {
-      p[(base + 2 * i) * ld] = e0;
-      p[(base + 2 * i + 1) * ld] = e1;
-      p[(base + 2 * M + 2 * i) * ld] = e2;
-      p[(base + 2 * M + 2 * i + 1) * ld] = e3;
-    }
-    if (first) {
-      p[(base + 4 * M) * ld] = f0;
-      p[(base + 4 * M + 1) * ld] = f1;
-    }
-  }
-};
-
-// Residual rows go through StagedSink (false) or DirectSink (true).
-constexpr bool kDirectResidualStores = false;
 
 // Rolls out one sample on the G lanes of its group and returns the group's
 // cost 1/2 ||r||^2 (identical in every lane of the group; 0 without COST,
@@ -298,6 +296,23 @@ __device__ __forceinline__ T chain_rollout(const ChainDev<T>& cd, int N,
   return T(0.5) * cost;
 }
 
+// out[0] = (sum of v over the block) / 2, in a fixed order; all threads of
+// the block must call it.
+template <typename T>
+__device__ __forceinline__ void block_half_sum(T v, T* out) {
+  __shared__ T part[kBlock / kWave];
+#pragma unroll
+  for (int off = kWave / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T t = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) t += part[w];
+    out[0] = T(0.5) * t;
+  }
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
 // b % 8).  Logical block g = (b % 8) * (gridDim.x / 8) + b / 8 gives each XCD
 // a contiguous range of samples, so the neighbouring 64-byte row segments of
@@ -318,7 +333,7 @@ __device__ __forceinline__ void rollout_chain_block(
     unsigned char* ctl_raw) {
   constexpr int kSpb = kBlock / G;
   // residual staging tile of StagedSink (one allocation for both control paths)
-  __shared__ T tile[2][FL][StagedSink<T, G, FL>::kRows][StagedSink<T, G, FL>::kLd];
+  __shared__ T tile[2][FL * StagedSink<T, G, FL>::kRows][StagedSink<T, G, FL>::kLd];
   if (g >= nblocks) return;  // whole padding block: no barrier is shared with it
   const int ncol = K + (c0 ? 1 : 0);
   const int grp = threadIdx.x / G;
@@ -327,12 +342,38 @@ __device__ __forceinline__ void rollout_chain_block(
   const int col = valid ? gcol : ncol - 1;  // idle groups repeat a valid column, never store
   const bool nominal = col == K;
   const int n = 2 * N;
-  // the cost terms only where a cost is stored (C, or the nominal's c0)
-  const bool want_cost =
-      C != nullptr || (c0 != nullptr && g * kSpb <= K && K < (g + 1) * kSpb);  // uniform
+  // vector stores of residual rows need 4-element aligned rows
+  const bool vec = R != nullptr && ldr % 4 == 0 &&
+                   reinterpret_cast<uintptr_t>(R) % (4 * sizeof(T)) == 0;
+  const bool staged = R != nullptr || r0 != nullptr;
+  const bool has_nominal = c0 != nullptr && g * kSpb <= K && K < (g + 1) * kSpb;  // uniform
+  // cost terms in the rollout only where C is stored, or for a nominal whose
+  // residual rows are not staged (with staged rows its c0 is the half sum of
+  // squares that the sink collects)
+  const bool want_cost = C != nullptr || (!staged && has_nominal);
   auto run = [&](const auto& ctrl, auto& sink) -> T {
     return want_cost ? chain_rollout<T, G, true>(cd, N, x0, q, r, xref, ctrl, sink)
                      : chain_rollout<T, G, false>(cd, N, x0, q, r, xref, ctrl, sink);
+  };
+  auto finish = [&](T c, T csum) {
+    if (valid && (threadIdx.x & (G - 1)) == 0) {
+      if (nominal) {
+        if (!staged) c0[0] = c;
+      } else if (C != nullptr) {
+        C[col] = c;
+      }
+    }
+    if (staged && has_nominal) block_half_sum(csum, c0);
+  };
+  auto go = [&](const auto& ctrl) {
+    if (staged) {
+      StagedSink<T, G, FL> sink{tile, R, ldr, r0, K, g * kSpb, cd.M, grp, N, vec};
+      const T c = run(ctrl, sink);
+      finish(c, sink.csum);
+    } else {
+      NoSink sink;
+      finish(run(ctrl, sink), T(0));
+    }
   };
   if (stage_ctl) {
     // the block's controls U + W[:, s] in one coalesced burst: ctl[idx][sample]
@@ -346,40 +387,9 @@ __device__ __forceinline__ void rollout_chain_block(
       ctl[e] = u;
     }
     __syncthreads();
-    CtrlStaged<T> ctrl{ctl, kSpb, grp};
-    T c;
-    if ((R != nullptr || r0 != nullptr) && kDirectResidualStores) {
-      DirectSink<T> sink{R, ldr, r0, K, col, cd.M, valid};
-      c = run(ctrl, sink);
-    } else if (R != nullptr || r0 != nullptr) {
-      StagedSink<T, G, FL> sink{tile, R, ldr, r0, K, col0, cd.M, grp, N};
-      c = run(ctrl, sink);
-    } else {
-      NoSink sink;
-      c = run(ctrl, sink);
-    }
-    if (valid && (threadIdx.x & (G - 1)) == 0) {
-      if (nominal)
-        c0[0] = c;
-      else if (C != nullptr)
-        C[col] = c;
-    }
-    return;
-  }
-  CtrlPerturbed<T> ctrl{U, W, ldw, (nominal || W == nullptr) ? -1 : col};
-  T c;
-  if (R != nullptr || r0 != nullptr) {
-    StagedSink<T, G, FL> sink{tile, R, ldr, r0, K, g * kSpb, cd.M, grp, N};
-    c = run(ctrl, sink);
+    go(CtrlStaged<T>{ctl, kSpb, grp});
   } else {
-    NoSink sink;
-    c = run(ctrl, sink);
-  }
-  if (valid && (threadIdx.x & (G - 1)) == 0) {
-    if (nominal)
-      c0[0] = c;
-    else if (C != nullptr)
-      C[col] = c;
+    go(CtrlPerturbed<T>{U, W, ldw, (nominal || W == nullptr) ? -1 : col});
   }
 }
 
