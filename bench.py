@@ -365,8 +365,8 @@ def main():
     chunk = min(args.steps, args.graph_chunk)
     reps = max(1, args.steps // chunk)
     steps = reps * chunk
-    # In a graph the factorisation of G = W W^T (which needs only W) runs on a
-    # side stream under the rollout; eager launches keep one stream.
+    # In a graph the factorisation of G = W W^T (which needs only W) runs one
+    # iteration ahead on a side stream; eager launches keep one stream.
     solver = GNMPPI(dp, w.x0, st, seed=w.noise_seed, max_iters=chunk + 1, overlap=not args.eager)
     graph = solver.capture(chunk) if not args.eager else None
     for _ in range(max(1, args.warmup // chunk)):

@@ -72,11 +72,14 @@ class GNMPPI:
     def __init__(self, dprob: DeviceProblem, x0, settings, seed: int = 1, U0=None,
                  sampler: str = "gaussian", max_iters: int | None = None, overlap: bool = False):
         self.p = dprob
-        # G = W W^T and its inverse depend only on W: with ``overlap`` they are
-        # factored on a side stream while the rollout and the sample
-        # contraction S run (LS estimator only).  Worth it inside a captured
-        # graph; with eager launches the cross-stream waits cost more than
-        # the overlap saves, hence off by default.
+        # G = W W^T and its inverse depend only on W, and W only on the seed
+        # and the iteration: with ``overlap`` (LS estimator only) a side
+        # stream draws its own copy of the next iteration's W and factors its
+        # G into a second workspace while the main stream finishes the
+        # current iteration and rolls out the next; the main stream joins it
+        # just before J = S G^{-1}.  Worth it inside a captured graph; with
+        # eager launches the cross-stream waits cost more than the overlap
+        # saves, hence off by default.
         self.overlap = overlap and settings.jacobian == "ls"
         self.side = torch.cuda.Stream(device=dprob.device) if self.overlap else None
         self.s = settings
@@ -104,6 +107,13 @@ class GNMPPI:
         self.status = torch.zeros(iters if iters else 1, 3, dtype=torch.int32, device=dev)
         code = _lib.F32 if dt == torch.float32 else _lib.F64
         self.work_j = _workspace(_lib.gnmppi_jacobian_workspace(code, m, n, K), dev)
+        self.works = [self.work_j]
+        self.W_side = None
+        if self.overlap:
+            # iteration it uses works[it % 2]; the side stream fills the other
+            self.works.append(_workspace(_lib.gnmppi_jacobian_workspace(code, m, n, K), dev))
+            self.W_side = torch.zeros_like(self.W)
+        self._gram_for = None  # iteration whose G^{-1} the side stream has been given
         self.work_g = _workspace(_lib.gnmppi_ggn_workspace(code, m, n), dev)
         self.method = _lib.JAC_LS if settings.jacobian == "ls" else _lib.JAC_MC
         if dt == torch.float32:
@@ -114,43 +124,61 @@ class GNMPPI:
         s = self.s
         return sigma_schedule(s.sigma0, s.beta, s.sigma_min, it)
 
-    def step(self, it: int, marks=None):
+    def _sample(self, W, it: int):
+        if self.sampler == "sigma_points":
+            _lib.gnmppi_sigma_points(W, self.sigma(it))
+        else:
+            _lib.gnmppi_sample(W, self.sigma(it), self.seed, it, antithetic=self.s.antithetic,
+                               K=self.K)
+
+    def _side_gram(self, it: int):
+        """Enqueues on the side stream: W of iteration ``it`` (the same draws
+        as the main stream's, into W_side) and G^{-1} into works[it % 2].
+        Ordered after all work enqueued so far on the current stream, so the
+        last reads of that workspace (iteration it - 2) and of W_side are
+        done."""
+        K = self.K
+        self.side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(self.side):
+            W2 = self.W_side[:, :K]
+            self._sample(W2, it)
+            _lib.gnmppi_perturbation_gram(W2, self.works[it % 2], self.m, self.status[it, 2:3], K)
+        self._gram_for = it
+
+    def step(self, it: int, marks=None, ahead: bool = True):
         """One iteration of Alg. 1: GetJacobian, full GGN step, line search,
         apply; the covariance shrink enters through ``sigma(it)``.  With
         ``marks`` (a dict name -> list), a pair of timing events is recorded
-        around each library call on the current stream."""
+        around each library call on the current stream.  With overlap and
+        ``ahead``, the side stream's work for iteration it + 1 is enqueued
+        once J of this iteration no longer needs the side stream."""
         K, sig = self.K, self.sigma(it)
         W = self.W[:, :K]
+        work = self.works[it % 2] if self.overlap else self.work_j
+        if self.overlap and self._gram_for != it:
+            self._side_gram(it)  # not enqueued by a preceding step
         tick = _Ticker(marks)
         tick.start("sample")
-        if self.sampler == "sigma_points":
-            _lib.gnmppi_sigma_points(W, sig)
-        else:
-            _lib.gnmppi_sample(W, sig, self.seed, it, antithetic=self.s.antithetic, K=K)
-        if self.overlap:
-            sampled = torch.cuda.Event()
-            sampled.record()
+        self._sample(W, it)
         tick.next("rollout")
         # residuals and the nominal cost only: the step never reads C
         _lib.gnmppi_rollout(self.p, self.x0, self.U, W, K, self.R[:, :K], None, self.r0, self.c0)
-        if self.overlap:
-            # enqueued after the rollout so that a captured graph keeps the
-            # rollout on the sampling queue and forks only the W-only work
-            self.side.wait_event(sampled)
-            with torch.cuda.stream(self.side):
-                _lib.gnmppi_perturbation_gram(W, self.work_j, self.m, self.status[it, 2:3], K)
         tick.next("jacobian")
         if self.overlap:
             # S = dR W^T needs only the rollout; the join with the side stream
             # comes just before J = S G^{-1}
             method = self.method | _lib.JAC_GRAM_READY
-            _lib.gnmppi_reconstruct_jacobian(self.R[:, :K], self.r0, W, self.J, self.work_j,
+            _lib.gnmppi_reconstruct_jacobian(self.R[:, :K], self.r0, W, self.J, work,
                                              method | _lib.JAC_S_ONLY, sig * sig,
                                              self.status[it, 0:1], K)
             torch.cuda.current_stream().wait_stream(self.side)
-            _lib.gnmppi_reconstruct_jacobian(self.R[:, :K], self.r0, W, self.J, self.work_j,
+            _lib.gnmppi_reconstruct_jacobian(self.R[:, :K], self.r0, W, self.J, work,
                                              method | _lib.JAC_APPLY_ONLY, sig * sig,
                                              self.status[it, 0:1], K)
+            if ahead and it + 1 < self.status.shape[0]:
+                self._side_gram(it + 1)
+            else:
+                self._gram_for = None
         else:
             _lib.gnmppi_reconstruct_jacobian(self.R[:, :K], self.r0, W, self.J, self.work_j,
                                              self.method, sig * sig, self.status[it, 0:1], K)
@@ -173,13 +201,16 @@ class GNMPPI:
         side = torch.cuda.Stream(device=self.p.device)
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):  # warm-up outside capture, as torch requires
-            self.step(it0)
+            self.step(it0, ahead=False)
         torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
+            # the first iteration enqueues its own side-stream work; the last
+            # enqueues none, so every fork is joined inside the graph
             for it in range(it0, it0 + iters):
-                self.step(it)
+                self.step(it, ahead=it + 1 < it0 + iters)
+        self._gram_for = None
         return graph
 
     def solve(self, iters: int | None = None, events: bool = False):
@@ -191,7 +222,7 @@ class GNMPPI:
             e0.record()
             evs.append(e0)
         for it in range(iters):
-            self.step(it)
+            self.step(it, ahead=it + 1 < iters)
             if events:
                 e = torch.cuda.Event(enable_timing=True)
                 e.record()

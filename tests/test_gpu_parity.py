@@ -554,8 +554,9 @@ def test_c1_solver_with_and_without_stream_overlap(overlap):
 @pytest.mark.parametrize("overlap", [False, True])
 @pytest.mark.parametrize("name", ["c1", "c2"])
 def test_graph_replays_match_eager_iterations(name, overlap):
-    # with overlap the W-only half runs on a side stream with its own copy of
-    # W and a workspace per iteration: the same arithmetic, so bit-identical
+    # with overlap the W-only half runs one iteration ahead on a side stream,
+    # with its own draw of W and two alternating workspaces: the same
+    # arithmetic, so bit-identical
     w = wl.get(name)
     dp = DeviceProblem(w.problem, w.dtype)
     eager = GNMPPI(dp, w.x0, w.settings, seed=5, max_iters=3)
