@@ -70,17 +70,25 @@ class GNMPPI:
     Philox normals) or "sigma_points" (Method E, the 2n-point Dirac mixture)."""
 
     def __init__(self, dprob: DeviceProblem, x0, settings, seed: int = 1, U0=None,
-                 sampler: str = "gaussian", max_iters: int | None = None, overlap: bool = False):
+                 sampler: str = "gaussian", max_iters: int | None = None, overlap=False):
         self.p = dprob
         # G = W W^T and its inverse depend only on W, and W only on the seed
-        # and the iteration: with ``overlap`` (LS estimator only) a side
-        # stream draws its own copy of the next iteration's W and factors its
-        # G into a second workspace while the main stream finishes the
-        # current iteration and rolls out the next; the main stream joins it
-        # just before J = S G^{-1}.  Worth it inside a captured graph; with
-        # eager launches the cross-stream waits cost more than the overlap
-        # saves, hence off by default.
-        self.overlap = overlap and settings.jacobian == "ls"
+        # and the iteration, so (LS estimator only) they can be factored on a
+        # side stream that the main stream joins just before J = S G^{-1}.
+        # overlap = "ahead" (or True): the side stream draws its own copy of
+        # the next iteration's W and factors its G into a second workspace
+        # while the main stream finishes the current iteration and rolls out
+        # the next.  overlap = "same": it forks after this iteration's sampler
+        # and factors G under the rollout and S.  Which one is faster depends
+        # on the sizes (the cross-stream edges of a graph cost a few us each);
+        # inside a captured graph either beats a single stream, with eager
+        # launches the waits cost more than the overlap saves, hence off by
+        # default.
+        if overlap not in (False, True, "ahead", "same"):
+            raise ValueError(f"overlap must be False, True, 'ahead' or 'same', not {overlap!r}")
+        mode = "ahead" if overlap is True else overlap
+        self.overlap = bool(mode) and settings.jacobian == "ls"
+        self.ahead = self.overlap and mode == "ahead"
         self.side = torch.cuda.Stream(device=dprob.device) if self.overlap else None
         self.s = settings
         self.seed = int(seed)
@@ -109,7 +117,7 @@ class GNMPPI:
         self.work_j = _workspace(_lib.gnmppi_jacobian_workspace(code, m, n, K), dev)
         self.works = [self.work_j]
         self.W_side = None
-        if self.overlap:
+        if self.ahead:
             # iteration it uses works[it % 2]; the side stream fills the other
             self.works.append(_workspace(_lib.gnmppi_jacobian_workspace(code, m, n, K), dev))
             self.W_side = torch.zeros_like(self.W)
@@ -149,20 +157,29 @@ class GNMPPI:
         """One iteration of Alg. 1: GetJacobian, full GGN step, line search,
         apply; the covariance shrink enters through ``sigma(it)``.  With
         ``marks`` (a dict name -> list), a pair of timing events is recorded
-        around each library call on the current stream.  With overlap and
-        ``ahead``, the side stream's work for iteration it + 1 is enqueued
-        once J of this iteration no longer needs the side stream."""
+        around each library call on the current stream.  With overlap
+        "ahead" and ``ahead``, the side stream's work for iteration it + 1 is
+        enqueued once J of this iteration no longer needs the side stream."""
         K, sig = self.K, self.sigma(it)
         W = self.W[:, :K]
-        work = self.works[it % 2] if self.overlap else self.work_j
-        if self.overlap and self._gram_for != it:
+        work = self.works[it % 2] if self.ahead else self.work_j
+        if self.ahead and self._gram_for != it:
             self._side_gram(it)  # not enqueued by a preceding step
         tick = _Ticker(marks)
         tick.start("sample")
         self._sample(W, it)
+        if self.overlap and not self.ahead:
+            sampled = torch.cuda.Event()
+            sampled.record()
         tick.next("rollout")
         # residuals and the nominal cost only: the step never reads C
         _lib.gnmppi_rollout(self.p, self.x0, self.U, W, K, self.R[:, :K], None, self.r0, self.c0)
+        if self.overlap and not self.ahead:
+            # enqueued after the rollout so that a captured graph keeps the
+            # rollout on the sampling queue and forks only the W-only work
+            self.side.wait_event(sampled)
+            with torch.cuda.stream(self.side):
+                _lib.gnmppi_perturbation_gram(W, work, self.m, self.status[it, 2:3], K)
         tick.next("jacobian")
         if self.overlap:
             # S = dR W^T needs only the rollout; the join with the side stream
@@ -175,10 +192,11 @@ class GNMPPI:
             _lib.gnmppi_reconstruct_jacobian(self.R[:, :K], self.r0, W, self.J, work,
                                              method | _lib.JAC_APPLY_ONLY, sig * sig,
                                              self.status[it, 0:1], K)
-            if ahead and it + 1 < self.status.shape[0]:
-                self._side_gram(it + 1)
-            else:
-                self._gram_for = None
+            if self.ahead:
+                if ahead and it + 1 < self.status.shape[0]:
+                    self._side_gram(it + 1)
+                else:
+                    self._gram_for = None
         else:
             _lib.gnmppi_reconstruct_jacobian(self.R[:, :K], self.r0, W, self.J, self.work_j,
                                              self.method, sig * sig, self.status[it, 0:1], K)
