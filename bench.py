@@ -350,6 +350,8 @@ def main():
     ap.add_argument("--mppi-iters", type=int, default=1500)
     ap.add_argument("--graph-chunk", type=int, default=50, help="iterations per captured graph")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graphs")
+    ap.add_argument("--overlap", choices=("auto", "ahead", "same"), default="auto",
+                    help="side-stream schedule of the graphs (auto: the faster of the two)")
     ap.add_argument("--kernel-reps", type=int, default=50, help="rollout launches for the roofline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
@@ -397,7 +399,12 @@ def main():
     # In a graph the factorisation of G = W W^T (which needs only W) runs on a
     # side stream, in the faster of the two schedules; eager launches keep one
     # stream.
-    overlap = False if args.eager else pick_overlap(dp, w.x0, st, seed=w.noise_seed, iters=chunk)
+    if args.eager:
+        overlap = False
+    elif args.overlap == "auto":
+        overlap = pick_overlap(dp, w.x0, st, seed=w.noise_seed, iters=chunk)
+    else:
+        overlap = args.overlap
     progress(f"side-stream schedule: {overlap}")
     solver = GNMPPI(dp, w.x0, st, seed=w.noise_seed, max_iters=chunk + 1, overlap=overlap)
     graph = solver.capture(chunk) if not args.eager else None
@@ -492,7 +499,7 @@ def main():
         "iteration_over_rollout": ms_per_step * 1e3 / per_call_us["rollout_kernel"],
         "timed_with": "eager launches" if args.eager else
         f"HIP graph replays of {chunk} iterations, G = W W^T factored on a side stream "
-        f"(schedule {overlap!r}, the faster of two timed at start-up)",
+        f"(schedule {overlap!r}" + (", the faster of two timed at start-up)" if args.overlap == "auto" else ")"),
         "roofline": roofline,
     }
 
