@@ -187,32 +187,26 @@ struct StagedSink {
               V{tile[buf][fr][sv], tile[buf][fr][sv + 1], tile[buf][fr][sv + 2],
                 tile[buf][fr][sv + 3]};
       }
-      // the block that holds column K: its last R columns and the nominal,
-      // one row per thread (the bounds are uniform, so the stores need no
-      // divergent branches)
+      // the block that holds column K: its last R columns one row per
+      // thread (the bounds are uniform, so the stores need no divergent
+      // branches)
       const int ctail = col0 + nvec * kVec, cend = min(col0 + kSpb, K);
-      const bool nom = col0 <= K && K < col0 + kSpb;
-      if (ctail < cend || nom) {
-        for (int fr = threadIdx.x; fr < nfr; fr += kBlock) {
+      if (ctail < cend)
+        for (int fr = threadIdx.x; fr < nfr; fr += kBlock)
           for (int c = ctail; c < cend; ++c) R[(base + fr) * ldr + c] = tile[buf][fr][c - col0];
-          if (nom) {
-            const T v = tile[buf][fr][K - col0];
-            if (r0) r0[base + fr] = v;
-            csum += v * v;
-          }
-        }
-      }
-    } else {
+    } else if (R) {
       for (int idx = threadIdx.x; idx < nfr * kSpb; idx += kBlock) {
         const int fr = idx / kSpb, sc = idx % kSpb;
-        const int c = col0 + sc;
-        const T v = tile[buf][fr][sc];
-        if (c < K) {
-          if (R) R[(base + fr) * ldr + c] = v;
-        } else if (c == K) {
-          if (r0) r0[base + fr] = v;
-          csum += v * v;
-        }
+        if (col0 + sc < K) R[(base + fr) * ldr + col0 + sc] = tile[buf][fr][sc];
+      }
+    }
+    // the nominal column, one row per thread whatever the layout of R (so
+    // c0 sums the same terms in the same order)
+    if (col0 <= K && K < col0 + kSpb) {
+      for (int fr = threadIdx.x; fr < nfr; fr += kBlock) {
+        const T v = tile[buf][fr][K - col0];
+        if (r0) r0[base + fr] = v;
+        csum += v * v;
       }
     }
   }

@@ -142,6 +142,51 @@ def test_rollout_nominal_only_and_single_sample(dtype):
     assert_parity(host(C1), [ocp.cost(rp, x0r, U + W1[:, 0])], dtype, "C1")
 
 
+@pytest.mark.parametrize("K", [61, 65, 4090])
+def test_rollout_residual_layouts_agree(K):
+    # R with an odd leading dimension takes the scalar residual stores, the
+    # padded R the 4-sample vector stores; both, and the ragged last chunk
+    # left of the nominal column, must give the same bits (and c0 the same
+    # sum of the staged nominal rows)
+    prob, x0 = wl.chain_problem(n_masses=16, N=9, seed=12)
+    dp = DeviceProblem(prob, "f32")
+    rng = np.random.default_rng(K)
+    U = rnd(0.2 * rng.standard_normal(prob.n), "f32")
+    W = rnd(0.3 * rng.standard_normal((prob.n, K)), "f32")
+    x0d, Ud, Wd = to_dev(rnd(x0, "f32"), "f32"), to_dev(U, "f32"), padded(W, "f32")
+    outs = []
+    for R, aligned in ((padded(np.zeros((prob.m, K)), "f32"), True),
+                       (torch.zeros(prob.m, K + 1, dtype=torch.float32, device=device())[:, :K],
+                        False)):
+        assert (R.stride(0) % 4 == 0) == aligned
+        r0, c0 = to_dev(np.zeros(prob.m), "f32"), to_dev(np.zeros(1), "f32")
+        _lib.gnmppi_rollout(dp, x0d, Ud, Wd, K, R, None, r0, c0)
+        _sync()
+        outs.append((host(R), host(r0), host(c0)))
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a, b)
+    rp = round_problem(prob, "f32")
+    cols = [0, K // 2, K - 1]
+    R_ref = np.stack([ocp.residual(rp, rnd(x0, "f32"), U + W[:, c]) for c in cols], axis=1)
+    assert_parity(outs[0][0][:, cols], R_ref, "f32", "R sampled columns")
+    assert_parity(outs[0][2], [ocp.cost(rp, rnd(x0, "f32"), U)], "f32", "c0")
+
+
+@pytest.mark.parametrize("schedule", ["ahead", "same"])
+def test_eager_steps_with_a_side_stream_match_one_stream(schedule):
+    w = wl.c2()
+    dp = DeviceProblem(w.problem, w.dtype)
+    ref = GNMPPI(dp, w.x0, w.settings, seed=9, max_iters=3)
+    two = GNMPPI(dp, w.x0, w.settings, seed=9, max_iters=3, overlap=schedule)
+    for it in range(3):
+        ref.step(it)
+        two.step(it, ahead=it + 1 < 3)
+    _sync()
+    np.testing.assert_array_equal(host(two.U), host(ref.U))
+    np.testing.assert_array_equal(host(two.info), host(ref.info))
+    assert (two.history(3)[2] == 0).all()
+
+
 def test_chain_rest_pose_is_a_fixed_point_on_device():
     prob, _ = wl.chain_problem(n_masses=16, N=50, seed=2)
     dp = DeviceProblem(prob, "f64")
