@@ -78,17 +78,22 @@ class GNMPPI:
         # overlap = "ahead" (or True): the side stream draws its own copy of
         # the next iteration's W and factors its G into a second workspace
         # while the main stream finishes the current iteration and rolls out
-        # the next.  overlap = "same": it forks after this iteration's sampler
-        # and factors G under the rollout and S.  Which one is faster depends
+        # the next.  overlap = "prefetch": the same, and the main stream rolls
+        # out with the side stream's W instead of drawing its own, so it joins
+        # before the rollout (no sampler on the main stream).  overlap =
+        # "same": it forks after this iteration's sampler and factors G under
+        # the rollout and S.  Which one is faster depends
         # on the sizes (the cross-stream edges of a graph cost a few us each);
         # inside a captured graph either beats a single stream, with eager
         # launches the waits cost more than the overlap saves, hence off by
         # default.
-        if overlap not in (False, True, "ahead", "same"):
-            raise ValueError(f"overlap must be False, True, 'ahead' or 'same', not {overlap!r}")
+        if overlap not in (False, True, "ahead", "prefetch", "same"):
+            raise ValueError("overlap must be False, True, 'ahead', 'prefetch' or 'same', "
+                             f"not {overlap!r}")
         mode = "ahead" if overlap is True else overlap
         self.overlap = bool(mode) and settings.jacobian == "ls"
-        self.ahead = self.overlap and mode == "ahead"
+        self.ahead = self.overlap and mode in ("ahead", "prefetch")
+        self.prefetch = self.overlap and mode == "prefetch"
         self.side = torch.cuda.Stream(device=dprob.device) if self.overlap else None
         self.s = settings
         self.seed = int(seed)
@@ -143,8 +148,8 @@ class GNMPPI:
         """Enqueues on the side stream: W of iteration ``it`` (the same draws
         as the main stream's, into W_side) and G^{-1} into works[it % 2].
         Ordered after all work enqueued so far on the current stream, so the
-        last reads of that workspace (iteration it - 2) and of W_side are
-        done."""
+        last reads of that workspace (iteration it - 2) and of W_side
+        (iteration it - 1, whose reads of W end with J) are done."""
         K = self.K
         self.side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(self.side):
@@ -167,7 +172,12 @@ class GNMPPI:
             self._side_gram(it)  # not enqueued by a preceding step
         tick = _Ticker(marks)
         tick.start("sample")
-        self._sample(W, it)
+        if self.prefetch:
+            # W and G^{-1} of this iteration come from the side stream
+            torch.cuda.current_stream().wait_stream(self.side)
+            W = self.W_side[:, :K]
+        else:
+            self._sample(W, it)
         if self.overlap and not self.ahead:
             sampled = torch.cuda.Event()
             sampled.record()
@@ -188,7 +198,8 @@ class GNMPPI:
             _lib.gnmppi_reconstruct_jacobian(self.R[:, :K], self.r0, W, self.J, work,
                                              method | _lib.JAC_S_ONLY, sig * sig,
                                              self.status[it, 0:1], K)
-            torch.cuda.current_stream().wait_stream(self.side)
+            if not self.prefetch:
+                torch.cuda.current_stream().wait_stream(self.side)
             _lib.gnmppi_reconstruct_jacobian(self.R[:, :K], self.r0, W, self.J, work,
                                              method | _lib.JAC_APPLY_ONLY, sig * sig,
                                              self.status[it, 0:1], K)

@@ -172,7 +172,7 @@ def test_rollout_residual_layouts_agree(K):
     assert_parity(outs[0][2], [ocp.cost(rp, rnd(x0, "f32"), U)], "f32", "c0")
 
 
-@pytest.mark.parametrize("schedule", ["ahead", "same"])
+@pytest.mark.parametrize("schedule", ["ahead", "prefetch", "same"])
 def test_eager_steps_with_a_side_stream_match_one_stream(schedule):
     w = wl.c2()
     dp = DeviceProblem(w.problem, w.dtype)
@@ -582,7 +582,7 @@ def test_c2_first_iteration_matches_oracle():
     assert costs[0] < ocp.cost(rp, rnd(w.x0, "f32"), np.zeros(p.n))
 
 
-@pytest.mark.parametrize("overlap", [False, "ahead", "same"])
+@pytest.mark.parametrize("overlap", [False, "ahead", "prefetch", "same"])
 def test_c1_solver_with_and_without_stream_overlap(overlap):
     w = wl.c1()
     solver = GNMPPI(DeviceProblem(w.problem, "f64"), w.x0, w.settings, seed=3, max_iters=2,
@@ -596,13 +596,13 @@ def test_c1_solver_with_and_without_stream_overlap(overlap):
     assert abs(costs[0] - cstar) / cstar < 1e-10
 
 
-@pytest.mark.parametrize("overlap", [False, "ahead", "same"])
+@pytest.mark.parametrize("overlap", [False, "ahead", "prefetch", "same"])
 @pytest.mark.parametrize("name", ["c1", "c2"])
 def test_graph_replays_match_eager_iterations(name, overlap):
     # with overlap the W-only half runs on a side stream ("ahead": one
     # iteration ahead, with its own draw of W and two alternating workspaces;
-    # "same": forked after this iteration's sampler): the same arithmetic, so
-    # bit-identical
+    # "prefetch": the same, and the main stream uses that W; "same": forked
+    # after this iteration's sampler): the same arithmetic, so bit-identical
     w = wl.get(name)
     dp = DeviceProblem(w.problem, w.dtype)
     eager = GNMPPI(dp, w.x0, w.settings, seed=5, max_iters=3)
