@@ -144,14 +144,18 @@ class GNMPPI:
             _lib.gnmppi_sample(W, self.sigma(it), self.seed, it, antithetic=self.s.antithetic,
                                K=self.K)
 
-    def _side_gram(self, it: int):
+    def _side_gram(self, it: int, after=None):
         """Enqueues on the side stream: W of iteration ``it`` (the same draws
         as the main stream's, into W_side) and G^{-1} into works[it % 2].
-        Ordered after all work enqueued so far on the current stream, so the
-        last reads of that workspace (iteration it - 2) and of W_side
-        (iteration it - 1, whose reads of W end with J) are done."""
+        Ordered after the event ``after`` (J of iteration it - 1), else after
+        all work enqueued so far on the current stream, so the last reads of
+        that workspace (iteration it - 2) and of W_side (iteration it - 1,
+        whose reads of W end with J) are done."""
         K = self.K
-        self.side.wait_stream(torch.cuda.current_stream())
+        if after is not None:
+            self.side.wait_event(after)
+        else:
+            self.side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(self.side):
             W2 = self.W_side[:, :K]
             self._sample(W2, it)
@@ -203,9 +207,14 @@ class GNMPPI:
             _lib.gnmppi_reconstruct_jacobian(self.R[:, :K], self.r0, W, self.J, work,
                                              method | _lib.JAC_APPLY_ONLY, sig * sig,
                                              self.status[it, 0:1], K)
+            j_done = None
             if self.ahead:
                 if ahead and it + 1 < self.status.shape[0]:
-                    self._side_gram(it + 1)
+                    # the next iteration's side work waits only for this J; it
+                    # is enqueued after the rest of this iteration, so that a
+                    # captured graph keeps the GGN step on J's queue
+                    j_done = torch.cuda.Event()
+                    j_done.record()
                 else:
                     self._gram_for = None
         else:
@@ -218,6 +227,8 @@ class GNMPPI:
         _lib.gnmppi_line_search(self.p, self.x0, self.U, self.dU, self.alpha, self.C_line,
                                 self.info[it])
         tick.stop()
+        if self.overlap and j_done is not None:
+            self._side_gram(it + 1, after=j_done)
 
     def capture(self, iters: int, it0: int = 0):
         """Captures iterations it0 .. it0 + iters - 1 into one HIP graph.
