@@ -113,6 +113,36 @@ __global__ void __launch_bounds__(256) sample_kernel(int n, int Kdraw, T sigma, 
   sample_block<T>(n, Kdraw, sigma, k0, k1, s0, s1, antithetic, W, ldw, blockIdx.x, blockIdx.y);
 }
 
+// FP32 with half the work per thread: block row y takes half y % 2 of the
+// Philox block y / 2 (rows 4 (y / 2) + 2 (y % 2) and the next), the same
+// numbers as sample_kernel<float>.  Twice the threads, one Box-Muller pair
+// each: the sampler is latency-bound at these sizes.
+__global__ void __launch_bounds__(256) sample_half_kernel(int n, int Kdraw, float sigma,
+                                                          uint32_t k0, uint32_t k1, uint32_t s0,
+                                                          uint32_t s1, int antithetic,
+                                                          float* __restrict__ W, int64_t ldw) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  const int b = blockIdx.y >> 1, half = blockIdx.y & 1;
+  const int row0 = 4 * b + 2 * half;
+  if (s >= Kdraw || row0 >= n) return;
+  const Philox4x32 x = philox4x32_10(
+      Philox4x32{static_cast<uint32_t>(s), static_cast<uint32_t>(b), s0, s1}, k0, k1);
+  float z[2];
+  if (half == 0)
+    box_muller_f32(x.c0, x.c1, z[0], z[1]);
+  else
+    box_muller_f32(x.c2, x.c3, z[0], z[1]);
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int row = row0 + t;
+    if (row < n) {
+      const float v = sigma * z[t];
+      W[row * ldw + s] = v;
+      if (antithetic) W[row * ldw + s + Kdraw] = -v;
+    }
+  }
+}
+
 // Batched: instance b draws with key b.seed and the stream id of the
 // iteration (the same numbers as a single-instance call with that seed);
 // tile = by * ceil(Kdraw / 256) + bx.
@@ -161,10 +191,11 @@ hipError_t launch_sample(int dtype, int n, int K, double sigma, uint64_t seed,
   const int Kdraw = antithetic ? K / 2 : K;
   const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
   const uint32_t s0 = static_cast<uint32_t>(stream_id), s1 = static_cast<uint32_t>(stream_id >> 32);
-  const int rows_per_block = dtype == GNMPPI_F32 ? 4 : 2;
-  dim3 grid((Kdraw + 255) / 256, (n + rows_per_block - 1) / rows_per_block);
+  // two rows per block row: FP32 one Box-Muller pair of a Philox block per
+  // thread, FP64 the block's two normals
+  dim3 grid((Kdraw + 255) / 256, (n + 1) / 2);
   if (dtype == GNMPPI_F32)
-    hipLaunchKernelGGL(sample_kernel<float>, grid, dim3(256), 0, st, n, Kdraw,
+    hipLaunchKernelGGL(sample_half_kernel, grid, dim3(256), 0, st, n, Kdraw,
                        static_cast<float>(sigma), k0, k1, s0, s1, antithetic,
                        static_cast<float*>(W), ldw);
   else
