@@ -1,11 +1,12 @@
 // Perturbation sampling (Sec. 3: W ~ N(0, Sigma); antithetic pairs as in
 // Sec. 5) and the Dirac-mixture set of Method E (Sec. 5).
 //
-// One thread draws one Philox4x32-10 block (Salmon et al., SC'11): four
-// 32-bit words for a fixed (column, row block).  FP32 turns the block into
-// four normals (two Box-Muller pairs), FP64 into two.  Threads of a wave take
-// consecutive columns, so every store is a coalesced 256/512-byte row segment
-// of the sample-fastest W.
+// A Philox4x32-10 block (Salmon et al., SC'11) gives four 32-bit words for a
+// fixed (column, row block).  FP32 turns the block into four normals (two
+// Box-Muller pairs; the single-instance sampler gives each pair its own
+// thread, the batched one draws the whole block per thread), FP64 into two.
+// Threads of a wave take consecutive columns, so every store is a coalesced
+// 256/512-byte row segment of the sample-fastest W.
 #include "batch.hpp"
 #include "common.hpp"
 #include "launch.hpp"
