@@ -111,6 +111,10 @@ def load(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # torch first: the HIP runtime that torch brings must be the one the
+    # library binds to, or the process holds two runtimes and the library's
+    # calls do not know torch's allocations and streams
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise FileNotFoundError(
             f"{path} is missing: build it first (python -m paper_2512_04579_amd.build)")
