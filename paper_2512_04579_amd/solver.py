@@ -79,8 +79,9 @@ class GNMPPI:
         # the next iteration's W and factors its G into a second workspace
         # while the main stream finishes the current iteration and rolls out
         # the next.  overlap = "prefetch": the same, and the main stream rolls
-        # out with the side stream's W instead of drawing its own, so it joins
-        # before the rollout (no sampler on the main stream).  overlap =
+        # out with the side stream's W instead of drawing its own (it waits
+        # for the side stream's sampler before the rollout; no sampler on the
+        # main stream).  overlap =
         # "same": it forks after this iteration's sampler and factors G under
         # the rollout and S.  Which one is faster depends
         # on the sizes (the cross-stream edges of a graph cost a few us each);
@@ -159,6 +160,9 @@ class GNMPPI:
         with torch.cuda.stream(self.side):
             W2 = self.W_side[:, :K]
             self._sample(W2, it)
+            if self.prefetch:
+                self._w_ready = torch.cuda.Event()
+                self._w_ready.record()
             _lib.gnmppi_perturbation_gram(W2, self.works[it % 2], self.m, self.status[it, 2:3], K)
         self._gram_for = it
 
@@ -177,8 +181,9 @@ class GNMPPI:
         tick = _Ticker(marks)
         tick.start("sample")
         if self.prefetch:
-            # W and G^{-1} of this iteration come from the side stream
-            torch.cuda.current_stream().wait_stream(self.side)
+            # W of this iteration comes from the side stream (its G^{-1} is
+            # joined before J as in "ahead")
+            torch.cuda.current_stream().wait_event(self._w_ready)
             W = self.W_side[:, :K]
         else:
             self._sample(W, it)
@@ -202,8 +207,7 @@ class GNMPPI:
             _lib.gnmppi_reconstruct_jacobian(self.R[:, :K], self.r0, W, self.J, work,
                                              method | _lib.JAC_S_ONLY, sig * sig,
                                              self.status[it, 0:1], K)
-            if not self.prefetch:
-                torch.cuda.current_stream().wait_stream(self.side)
+            torch.cuda.current_stream().wait_stream(self.side)
             _lib.gnmppi_reconstruct_jacobian(self.R[:, :K], self.r0, W, self.J, work,
                                              method | _lib.JAC_APPLY_ONLY, sig * sig,
                                              self.status[it, 0:1], K)
