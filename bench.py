@@ -86,15 +86,25 @@ def rollout_traffic(name: str, esize: int):
     return float(kv["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(w, budget_s: float):
-    """The oracle's GN-MPPI iteration timed on the host cores (FP64 NumPy)."""
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu's "Model name", read from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_iterations(w, budget_s: float):
+    """GN-MPPI iterations of the oracle on workload w for about budget_s
+    seconds; returns (iterations, seconds)."""
     import numpy as np
-    import threadpoolctl
 
     import workloads as wl
     from oracle import solvers
-    info = threadpoolctl.threadpool_info()
-    blas_threads = max([i.get("num_threads", 1) for i in info if i.get("user_api") == "blas"] or [1])
     p, st = w.problem, w.settings
     U = np.zeros(p.n)
     its, t0 = 0, time.perf_counter()
@@ -105,11 +115,45 @@ def cpu_baseline(w, budget_s: float):
         its += 1
         el = time.perf_counter() - t0
         if el >= budget_s:
-            break
-    return {"value": its / el, "unit": "iters/s", "cores": int(blas_threads), "kind": "oracle",
-            "sample": f"{its} GN-MPPI iterations of the {w.name} workload (K={st.K}, N={p.N}) "
-                      f"in FP64 NumPy, {el:.1f} s; host has {os.cpu_count()} logical CPUs",
-            "sample_steps_per_s": its * (st.K + 1 + st.n_alpha) * p.N / el}
+            return its, el
+
+
+def cpu_baseline(w, budget_s: float, single_budget_s: float):
+    """The oracle's GN-MPPI iteration timed on the host cores (FP64 NumPy):
+    with the BLAS using every host thread, then with one thread."""
+    import threadpoolctl
+
+    info = threadpoolctl.threadpool_info()
+    blas_threads = max([i.get("num_threads", 1) for i in info if i.get("user_api") == "blas"] or [1])
+    p, st = w.problem, w.settings
+    per_it = (st.K + 1 + st.n_alpha) * p.N
+    its, el = _oracle_iterations(w, budget_s)
+    out = {"value": its / el, "unit": "iters/s", "cores": int(blas_threads), "kind": "oracle",
+           "sample": f"{its} GN-MPPI iterations of the {w.name} workload (K={st.K}, N={p.N}) "
+                     f"in FP64 NumPy, {el:.1f} s, BLAS threads = {blas_threads}; host has "
+                     f"{os.cpu_count()} logical CPUs",
+           "cpu_model": cpu_model(), "logical_cpus": os.cpu_count(),
+           "sample_steps_per_s": its * per_it / el}
+    if single_budget_s > 0:
+        with threadpoolctl.threadpool_limits(limits=1, user_api="blas"):
+            its1, el1 = _oracle_iterations(w, single_budget_s)
+        out["single_thread"] = {"value": its1 / el1, "unit": "iters/s", "cores": 1,
+                                "sample": f"{its1} iterations, {el1:.1f} s, BLAS limited to one thread",
+                                "sample_steps_per_s": its1 * per_it / el1}
+    return out
+
+
+def reference_c3(inst):
+    """The oracle's C* of the judged c3 instances (Method A, FP64, written by
+    tests/golden/make_c3_reference_optima.py), checked against the shapes of
+    the batch being timed."""
+    with open(os.path.join(ROOT, "tests", "golden", "c3_reference_optima.json")) as f:
+        rows = json.load(f)["instances"]
+    for r in rows:
+        p, _, K = inst[r["index"]]
+        if (p.n_masses, p.N, int(K)) != (r["n_masses"], r["N"], r["K"]):
+            raise RuntimeError(f"c3 reference optima do not match instance {r['index']}")
+    return rows
 
 
 def pick_overlap(dp, x0, st, seed: int, iters: int = 50) -> str:
@@ -179,7 +223,7 @@ def bench_sweep(args):
             "timed_with": "HIP graph replays of 50 iterations per point", "sweep": rows}
 
 
-def bench_batched(args):
+def bench_batched(args, steps: int, warmup: int, tune: bool):
     """The batched form: ``--batch-count`` chain instances with M in 4..16,
     N in 20..80 and K in {512, 1024, 2048, 4096} (seeded), one GN-MPPI
     iteration for all of them per step, timed as HIP-graph replays after the
@@ -194,12 +238,13 @@ def bench_batched(args):
     st = wl.c2().settings
     L = st.n_alpha
     batch = BatchGNMPPI(inst, st, seed=1)
-    tune = autotune(batch, cache=None, log=progress)
-    chunk = max(1, min(args.steps, 10))
-    reps = max(1, args.steps // chunk)
+    tuned = autotune(batch, cache=None, log=progress) if tune else {
+        "tuning": "library default (an autotuner pick for this batch)"}
+    chunk = max(1, min(steps, 10))
+    reps = max(1, steps // chunk)
     steps = reps * chunk
     graph = batch.capture(chunk)
-    for _ in range(max(1, args.warmup // chunk)):
+    for _ in range(max(1, warmup // chunk)):
         graph.replay()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -223,16 +268,13 @@ def bench_batched(args):
     iter_bytes = 2 * r_bytes + 3 * w_bytes
     gbps = iter_bytes / (ms * 1e-3) / 1e9
 
-    # time to a 1e-3 gap for every instance, from U = 0; C* per instance from
-    # a longer run of the same solver (the nonlinear chains have no closed form)
+    # time to a 1e-3 gap from U = 0, judged on the seeded sample of instances
+    # whose C* the oracle computed (Method A, FP64); the batch solves all of
+    # them, the clock runs until every judged instance is within the gap
     del graph
-    judge = BatchGNMPPI(inst, st, seed=101, tuning=batch.tuning)
-    best = np.full(len(inst), np.inf)
-    jgraph = judge.capture(12)
-    jgraph.replay()
-    torch.cuda.synchronize()
-    best = judge.costs()  # after 12 iterations: the lowest cost the line search kept
-    del jgraph, judge
+    ref = reference_c3(inst)
+    judged = np.array([r["index"] for r in ref])
+    best = np.array([r["cstar"] for r in ref])
     run = BatchGNMPPI(inst, st, seed=1, tuning=batch.tuning)
     graphs = [run.capture(1, it0=it) for it in range(8)]  # one graph per iteration
     torch.cuda.synchronize()
@@ -244,7 +286,7 @@ def bench_batched(args):
         e = torch.cuda.Event(enable_timing=True)
         e.record()
         evs.append(e)
-        gaps.append((run.costs() - best) / np.abs(best))  # syncs; the times come from the events
+        gaps.append((run.costs()[judged] - best) / np.abs(best))  # syncs; the times come from the events
     gaps = np.array(gaps)
     del graphs
     t_all = None
@@ -253,18 +295,18 @@ def bench_batched(args):
             t_all = evs[0].elapsed_time(evs[it + 1]) * 1e-3
             break
     # the same instances one at a time: GN-MPPI from zero (one captured graph
-    # per iteration) and plain MPPI, on a seeded sample of 16 instances;
+    # per iteration) and plain MPPI, on the first 16 judged instances;
     # per-instance times summed and scaled to the whole batch
     from paper_2512_04579_amd.problem import DeviceProblem
     from paper_2512_04579_amd.solver import GNMPPI, PlainMPPI
     import dataclasses
-    pick = np.random.default_rng(3).choice(len(inst), size=min(16, len(inst)), replace=False)
+    pick = judged[:16]
     t_gn, t_mp, reached_mp = [], [], 0
-    for b in pick:
+    for i, b in enumerate(pick):
         p, x0, K = inst[b]
         dp = DeviceProblem(p, "f32")
         stb = dataclasses.replace(st, K=int(K))
-        cst = best[b]
+        cst = best[i]
         g = GNMPPI(dp, x0, stb, seed=1 + int(b), max_iters=8)
         gr = [g.capture(1, it0=it) for it in range(8)]
         g.U.zero_()
@@ -300,7 +342,7 @@ def bench_batched(args):
             t_mp.append(e0.elapsed_time(evs[hit[0]]) * 1e-3)
     gn_ok = [t for t in t_gn if t is not None]
     sequential = {
-        "sample": f"{len(pick)} of {len(inst)} instances (seeded), times summed and scaled by "
+        "sample": f"{len(pick)} of the {len(judged)} judged instances, times summed and scaled by "
                   f"{len(inst)}/{len(pick)}",
         "gn_mppi_single_instance_s": (sum(gn_ok) * len(inst) / len(gn_ok)) if gn_ok else None,
         "gn_mppi_reached": f"{len(gn_ok)}/{len(pick)} within 8 iterations",
@@ -312,7 +354,7 @@ def bench_batched(args):
         "metric": METRIC,
         "value": 1e3 / ms,
         "unit": "batched iters/s",
-        "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": ms,
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{len(inst)} chain MPC instances, M 4..16, N 20..80, "
@@ -325,76 +367,35 @@ def bench_batched(args):
         "roofline": {"kernel": "whole batched iteration", "bound": "hbm", "achieved": gbps,
                      "peak": PEAK["hbm_GBps"], "unit": "GB/s", "frac": gbps / PEAK["hbm_GBps"],
                      "traffic": None, "algorithmic_bytes": iter_bytes},
-        "autotune": tune,
-        "time_to_gap_s": {"all_instances": t_all, "gap_threshold": 1e-3,
+        "autotune": tuned,
+        "time_to_gap_s": {"all_judged_instances": t_all, "gap_threshold": 1e-3,
                           "one_instance_at_a_time": sequential,
                           "median_gap_per_iter": [float(np.median(g)) for g in gaps],
                           "max_gap_per_iter": [float(np.max(g)) for g in gaps],
-                          "cstar": "min cost over 12 iterations of an independent batched run"},
+                          "cstar": f"oracle Method A (FP64) on {len(judged)} seeded instances "
+                                   "(tests/golden/c3_reference_optima.json)",
+                          "judged_instances": [int(b) for b in judged]},
     }
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"],
-                    help="c3 = 1024 uneven chain instances through the batched iteration")
-    ap.add_argument("--batch-count", type=int, default=1024, help="instances of the c3 workload")
-    ap.add_argument("--sweep", action="store_true",
-                    help="chain16 scaling curves: iterations/s at K in 512..8192 and N in 20, 50, 80")
-    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle timing")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-time-to-gap", action="store_true")
-    ap.add_argument("--mppi-iters", type=int, default=1500)
-    ap.add_argument("--graph-chunk", type=int, default=50, help="iterations per captured graph")
-    ap.add_argument("--eager", action="store_true", help="time eager launches instead of graphs")
-    ap.add_argument("--overlap", choices=("auto", "ahead", "prefetch", "same"), default="auto",
-                    help="side-stream schedule of the graphs (auto: the fastest of the three)")
-    ap.add_argument("--kernel-reps", type=int, default=50, help="rollout launches for the roofline")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain device copy of known size (HBM counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "design is described but not built", file=sys.stderr)
-        sys.exit(2)
-
+def bench_single(w, args, steps_req: int, warmup: int):
+    """One workload through the single-instance solver: graph-timed
+    iterations, per-call times, the rollout kernel's roofline and the time to
+    a 1e-3 cost gap against the oracle's C*."""
     import numpy as np
     import torch
 
-    import workloads as wl
     from paper_2512_04579_amd import _lib
     from paper_2512_04579_amd.problem import DeviceProblem
     from paper_2512_04579_amd.solver import GNMPPI, PlainMPPI
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    _lib.load()
-    if args.copy_calibration:
-        a = torch.ones(64 * 2 ** 20, dtype=torch.float32, device="cuda")  # 256 MiB
-        b = torch.empty_like(a)
-        for _ in range(5):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4,
-                          "launches": 5}))
-        return
-
-    if args.workload == "c3":
-        print(json.dumps(bench_batched(args)))
-        return
-    if args.sweep:
-        print(json.dumps(bench_sweep(args)))
-        return
-    w = wl.get(args.workload)
     p, st = w.problem, w.settings
     dp = DeviceProblem(p, w.dtype)
     esize = 4 if w.dtype == "f32" else 8
     # The timed region replays HIP graphs of `chunk` captured iterations, so the
     # host enqueues one launch per chunk instead of ~12 kernels per iteration.
-    chunk = min(args.steps, args.graph_chunk)
-    reps = max(1, args.steps // chunk)
+    chunk = min(steps_req, args.graph_chunk)
+    reps = max(1, steps_req // chunk)
     steps = reps * chunk
     # In a graph the factorisation of G = W W^T (which needs only W) runs on a
     # side stream, in the fastest of the three schedules; eager launches keep
@@ -408,7 +409,7 @@ def main():
     progress(f"side-stream schedule: {overlap}")
     solver = GNMPPI(dp, w.x0, st, seed=w.noise_seed, max_iters=chunk + 1, overlap=overlap)
     graph = solver.capture(chunk) if not args.eager else None
-    for _ in range(max(1, args.warmup // chunk)):
+    for _ in range(max(1, warmup // chunk)):
         graph.replay() if graph else [solver.step(it) for it in range(chunk)]
     torch.cuda.synchronize()
     t_start = torch.cuda.Event(enable_timing=True)
@@ -454,7 +455,6 @@ def main():
     torch.cuda.synchronize()
     rollout_us = e0.elapsed_time(e1) * 1e3 / args.kernel_reps
     per_call_us["rollout_kernel"] = rollout_us
-    args.steps = steps
 
     K, L, N = solver.K, st.n_alpha, p.N
     work = algorithmic_work(p, K, L, esize)
@@ -479,11 +479,11 @@ def main():
 
     result = {
         "metric": METRIC,
-        "value": args.steps / (ms_total * 1e-3),
+        "value": steps / (ms_total * 1e-3),
         "unit": "iters/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -493,7 +493,7 @@ def main():
         "config": {"workload": w.description, "name": w.name, "nx": p.nx, "nu": p.nu, "N": N, "K": K,
                    "m": p.m, "n": p.n, "line_search_candidates": L, "jacobian": st.jacobian,
                    "contraction": st.contraction, "overlap": overlap},
-        "sample_steps_per_s": args.steps * (K + 1 + L) * N / (ms_total * 1e-3),
+        "sample_steps_per_s": steps * (K + 1 + L) * N / (ms_total * 1e-3),
         "host_wall_s": wall,
         "per_call": calls,
         "iteration_over_rollout": ms_per_step * 1e3 / per_call_us["rollout_kernel"],
@@ -583,9 +583,84 @@ def main():
                                    "plain_mppi_iters_run": args.mppi_iters, "cstar": cstar,
                                    "gap_threshold": 1e-3}
 
+    return result
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"],
+                    help="c3 = 1024 uneven chain instances through the batched iteration")
+    ap.add_argument("--batch-count", type=int, default=1024, help="instances of the c3 workload")
+    ap.add_argument("--sweep", action="store_true",
+                    help="chain16 scaling curves: iterations/s at K in 512..8192 and N in 20, 50, 80")
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle timing")
+    ap.add_argument("--cpu-single-budget", type=float, default=8.0,
+                    help="seconds of single-thread oracle timing (0: skip)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="c2 only: leave out the c4 and c3 objects of the default line")
+    ap.add_argument("--autotune", action="store_true",
+                    help="--workload c3: run the launch-shape autotuner before timing")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-time-to-gap", action="store_true")
+    ap.add_argument("--mppi-iters", type=int, default=1500)
+    ap.add_argument("--graph-chunk", type=int, default=50, help="iterations per captured graph")
+    ap.add_argument("--eager", action="store_true", help="time eager launches instead of graphs")
+    ap.add_argument("--overlap", choices=("auto", "ahead", "prefetch", "same"), default="auto",
+                    help="side-stream schedule of the graphs (auto: the fastest of the three)")
+    ap.add_argument("--kernel-reps", type=int, default=50, help="rollout launches for the roofline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "design is described but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads as wl
+    from paper_2512_04579_amd import _lib
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    _lib.load()
+    if args.copy_calibration:
+        a = torch.ones(64 * 2 ** 20, dtype=torch.float32, device="cuda")  # 256 MiB
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4,
+                          "launches": 5}))
+        return
+
+    if args.workload == "c3":
+        print(json.dumps(bench_batched(args, args.steps, args.warmup, tune=args.autotune)))
+        return
+    if args.sweep:
+        print(json.dumps(bench_sweep(args)))
+        return
+    w = wl.get(args.workload)
+    result = bench_single(w, args, args.steps, args.warmup)
+    if args.workload == "c2" and not args.no_extra:
+        # the precision split (c4) and the batched form (c3) in the same line:
+        # graph-timed iterations and time to the 1e-3 gap of each
+        progress("c4: precision split")
+        c4 = bench_single(wl.c4(), args, 50, 10)
+        for key in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data",
+                    "host_wall_s"):
+            c4.pop(key, None)
+        result["c4"] = c4
+        progress("c3: batched form (library default tuning)")
+        c3 = bench_batched(args, steps=10, warmup=10, tune=False)
+        for key in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
+            c3.pop(key, None)
+        result["c3"] = c3
     if not args.no_cpu_baseline:
         progress("timing the CPU oracle")
-        result["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+        result["cpu_baseline"] = cpu_baseline(w, args.cpu_budget, args.cpu_single_budget)
     print(json.dumps(result))
 
 

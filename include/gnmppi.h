@@ -220,11 +220,12 @@ int gnmppi_ggn_step(int32_t dtype, int32_t m, int32_t n, const void *J,
  * picks j* = the first index of the smallest finite cost, and applies
  * U <- U + alpha[j*] dU in place.  alpha: L step lengths (device, dtype),
  * 1 <= L <= 64.  C (optional): the L candidate costs.  info (optional,
- * device double[3]): {alpha[j*], C_j*, j*}; if no candidate cost is finite,
- * U is unchanged and info = {0, NaN, -1}. */
+ * device double[3]): {alpha[j*], C_j*, j*}.  status (optional, device
+ * int32): GNMPPI_OK, or GNMPPI_ENONFINITE if no candidate cost is finite --
+ * then U is unchanged and info = {0, NaN, -1}. */
 int gnmppi_line_search(const gnmppi_problem *p, const void *x0, void *U,
                        const void *dU, const void *alpha, int32_t L, void *C,
-                       double *info, void *stream);
+                       double *info, int32_t *status, void *stream);
 
 /* ---- batched iterations ----------------------------------------------------
  *
@@ -240,8 +241,9 @@ int gnmppi_line_search(const gnmppi_problem *p, const void *x0, void *U,
  * fields and q / r / x_ref are ignored).  Instance b: 3 <= n_masses <= 16,
  * 1 <= N <= 80, K even with K / 2 >= 2 N (antithetic pairs must span the
  * decisions), K <= 65536; device float32 x0 (4M), q (4M), r (2), x_ref (4M)
- * and U (2N, the iterate, updated in place); status (2 int32: Jacobian rank,
- * GGN positive definiteness, as the single-instance calls report them) and
+ * and U (2N, the iterate, updated in place); status (3 int32: Jacobian rank,
+ * GGN positive definiteness and line search, as the single-instance calls
+ * report them) and
  * info (3 doubles: alpha*, C*, j* of the last line search).  Instance b
  * draws its perturbations from Philox key seed + b and stream id = the
  * iteration index, exactly as gnmppi_sample with that seed would.

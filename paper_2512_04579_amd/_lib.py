@@ -86,7 +86,7 @@ SIGNATURES = {
     "gnmppi_ggn_step": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_int64, c_void_p, c_int64,
                                   c_double, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
     "gnmppi_line_search": (c_int32, [PROBLEM_P, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
-                                     c_void_p, c_void_p, c_void_p]),
+                                     c_void_p, c_void_p, c_void_p, c_void_p]),
     "gnmppi_batch_workspace": (c_size_t, [PROBLEM_P, c_int32, BATCH_P, BSET_P, BTUNE_P]),
     "gnmppi_batch_prepare": (c_int32, [PROBLEM_P, c_int32, BATCH_P, BSET_P, BTUNE_P, c_void_p, c_size_t]),
     "gnmppi_batch_iteration": (c_int32, [PROBLEM_P, c_int32, BATCH_P, BSET_P, BTUNE_P, c_void_p,
@@ -237,10 +237,10 @@ def gnmppi_ggn_step(J, r0, lm_lambda: float, dU, work, status=None, inc_r0: int 
         _ptr(work), work.numel() * work.element_size(), _ptr(status), _stream(stream)))
 
 
-def gnmppi_line_search(problem, x0, U, dU, alpha, C=None, info=None, stream=None):
+def gnmppi_line_search(problem, x0, U, dU, alpha, C=None, info=None, status=None, stream=None):
     _check("gnmppi_line_search", load().gnmppi_line_search(
         ctypes.byref(problem.c), _ptr(x0), _ptr(U), _ptr(dU), _ptr(alpha), alpha.numel(), _ptr(C),
-        _ptr(info), _stream(stream)))
+        _ptr(info), _ptr(status), _stream(stream)))
 
 
 def gnmppi_batch_workspace(shared, count, inst, settings, tuning) -> int:

@@ -72,7 +72,8 @@ class BatchGNMPPI:
         self.r = torch.tensor(np.concatenate([p.r for p in self.problems]), **f32)
         self.x_ref = torch.tensor(np.concatenate([p.x_ref for p in self.problems]), **f32)
         self.U = torch.zeros(int(self.n_off[-1]), **f32)
-        self.status = torch.zeros(self.count, 2, dtype=torch.int32, device=self.dev)
+        # per instance: Jacobian rank, GGN positive definiteness, line search
+        self.status = torch.zeros(self.count, 3, dtype=torch.int32, device=self.dev)
         self.info = torch.zeros(self.count, 3, dtype=torch.float64, device=self.dev)
         arr = (_lib.GnmppiBatchInstance * self.count)()
         for b, (p, _, K) in enumerate(instances):

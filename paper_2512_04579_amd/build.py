@@ -19,7 +19,10 @@ BUILD_DIR = os.path.join(HERE, "_build")
 LIB_PATH = os.path.join(HERE, "libgnmppi.so")
 ARCH = "gfx950"
 
-SOURCES = ["abi.cpp", "batch.cpp", "sample.hip", "rollout.hip", "mppi.hip", "gemm.hip", "dense.hip",
+# Longest compiles first (the sweep units instantiate one kernel per 16-row
+# class), so the parallel build ends with the short ones.
+SOURCES = ["sweep_batch_inv.hip", "sweep_batch_dir.hip", "sweep_f32.hip", "sweep_f64.hip",
+           "dense.hip", "gemm.hip", "rollout.hip", "abi.cpp", "batch.cpp", "sample.hip", "mppi.hip",
            "mlp.hip"]
 
 # Packed FP32 VALU ops are switched off for every HIP translation unit.

@@ -150,12 +150,14 @@ int gnmppi_ggn_step(int32_t dtype, int32_t m, int32_t n, const void* J, int64_t 
 }
 
 int gnmppi_line_search(const gnmppi_problem* p, const void* x0, void* U, const void* dU,
-                       const void* alpha, int32_t L, void* C, double* info, void* stream) {
+                       const void* alpha, int32_t L, void* C, double* info, int32_t* status,
+                       void* stream) {
   if (!problem_ok(p) || !sizes_fit(p) || x0 == nullptr || U == nullptr || dU == nullptr ||
       alpha == nullptr)
     return GNMPPI_EINVAL;
   if (L < 1 || L > 64) return GNMPPI_EINVAL;
-  return status_of(gnm::launch_line_search(*p, x0, U, dU, alpha, L, C, info, as_stream(stream)));
+  return status_of(
+      gnm::launch_line_search(*p, x0, U, dU, alpha, L, C, info, status, as_stream(stream)));
 }
 
 int64_t gnmppi_mlp_param_count(int32_t n_in, int32_t n_hidden, int32_t n_out) {
@@ -217,6 +219,6 @@ const char* gnmppi_status_string(int32_t status) {
   }
 }
 
-int32_t gnmppi_abi_version(void) { return 1; }
+int32_t gnmppi_abi_version(void) { return 2; }
 
 }  // extern "C"

@@ -29,7 +29,7 @@ struct BatchInst {
   const float* r;
   const float* xref;
   float* U;
-  int32_t* status;  // [0] Jacobian (G rank), [1] GGN (positive definite)
+  int32_t* status;  // [0] Jacobian (G rank), [1] GGN (positive definite), [2] line search
   double* info;     // alpha*, C*, j* of the last line search
   float* W;
   float* R;

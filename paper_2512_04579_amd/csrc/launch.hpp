@@ -21,7 +21,7 @@ hipError_t launch_rollout(const gnmppi_problem& p, const void* x0, const void* U
                           void* C, void* r0, void* c0, hipStream_t st);
 hipError_t launch_line_search(const gnmppi_problem& p, const void* x0, void* U,
                               const void* dU, const void* alpha, int L, void* C,
-                              double* info, hipStream_t st);
+                              double* info, int32_t* status, hipStream_t st);
 
 hipError_t launch_mppi_update(int dtype, int n, int K, const void* C, const void* W,
                               int64_t ldw, double temperature, void* U, void* weights,
@@ -68,6 +68,17 @@ hipError_t launch_contract(const ContractArgs<double>& a, int nsplit, hipStream_
 hipError_t launch_contract_bf16(int terms, int m, int n, int K, const float* R, int64_t ldr,
                                 const float* r0, const float* W, int64_t ldw, int nsplit,
                                 int split_len, float* part, int npad, hipStream_t st);
+
+// Symmetric sweep of an SPD matrix M (P x P, full, double) over its first
+// npiv pivots (sweep.hpp): kSweepInverse writes the inverse of the leading
+// block into inv_out (ldo), kSweepDirection writes the GGN direction
+// -(H^{-1} g) of M = [[H, g], [g^T, c]] into dir_out.  A failed pivot writes
+// fail_code to *status (else GNMPPI_OK).  P <= 208.
+enum SweepOut { kSweepInverse = 0, kSweepDirection = 1 };
+hipError_t launch_sweep(int P, int npiv, int mode, const double* M, float* inv_out, int64_t ldo,
+                        float* dir_out, int32_t* status, int fail_code, hipStream_t st);
+hipError_t launch_sweep(int P, int npiv, int mode, const double* M, double* inv_out, int64_t ldo,
+                        double* dir_out, int32_t* status, int fail_code, hipStream_t st);
 
 // Jacobian reconstruction; `work` holds the GEMM partials, G, G^{-1} and S.
 struct JacPlan {
@@ -132,6 +143,10 @@ hipError_t launch_batch_reduce_sym(int mode, const BatchInst* inst, const BatchL
                                    double lm_lambda, hipStream_t st);
 hipError_t launch_batch_sweep(int mode, int R, const BatchInst* inst, const BatchLaunch& L,
                               hipStream_t st);
+hipError_t launch_batch_sweep_mode0(int R, const BatchInst* inst, const BatchLaunch& L,
+                                    hipStream_t st);
+hipError_t launch_batch_sweep_mode1(int R, const BatchInst* inst, const BatchLaunch& L,
+                                    hipStream_t st);
 hipError_t launch_batch_reduce_rows(const BatchInst* inst, const BatchLaunch& L, hipStream_t st);
 hipError_t launch_batch_gram(int nt, const BatchInst* inst, const BatchLaunch& L, hipStream_t st);
 

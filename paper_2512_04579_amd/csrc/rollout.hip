@@ -95,10 +95,14 @@ struct CtrlLineStaged {
 // Right-hand side for mass i (lane i of the group).  The end mass moves with
 // the commanded velocity: its lane enters every step with v = u and inverse
 // mass im = 0, so dv = 0 keeps v = u through the RK4 stages and dp = v is
-// the commanded velocity with no per-stage select.
+// the commanded velocity with no per-stage select.  With G < 16 the last
+// lane of a group reads T_{i+1} from the first lane of the next sample's
+// group, which may be infinite if that sample diverged; inf * 0 would carry a
+// NaN into this sample, so lanes without a free mass select dv = 0 there (a
+// select, so finite results are unchanged bit for bit).
 template <typename T, int G>
 __device__ __forceinline__ void chain_rhs(T px, T py, T vx, T vy, const ChainDev<T>& cd, bool first,
-                                          T im, T& dpx, T& dpy, T& dvx, T& dvy) {
+                                          bool free_mass, T im, T& dpx, T& dpy, T& dvx, T& dvy) {
   T qx = 0, qy = 0;
   if constexpr (G > 1) {
     qx = dpp_move<kDppRowShr1>(px);
@@ -122,6 +126,10 @@ __device__ __forceinline__ void chain_rhs(T px, T py, T vx, T vy, const ChainDev
   dpy = vy;
   dvx = (nx - tx) * im;
   dvy = (ny - ty) * im;
+  if constexpr (G < 16) {
+    dvx = free_mass ? dvx : T(0);
+    dvy = free_mass ? dvy : T(0);
+  }
 }
 
 // Residual sinks of the chain rollout.  NoSink keeps only the cost.
@@ -258,16 +266,16 @@ __device__ __forceinline__ T chain_rollout(const ChainDev<T>& cd, int N,
         vy = u1;
       }
       T a_px, a_py, a_vx, a_vy, b_px, b_py, b_vx, b_vy;
-      chain_rhs<T, G>(px, py, vx, vy, cd, first, im, a_px, a_py, a_vx, a_vy);
+      chain_rhs<T, G>(px, py, vx, vy, cd, first, free_mass, im, a_px, a_py, a_vx, a_vy);
       T s_px = a_px, s_py = a_py, s_vx = a_vx, s_vy = a_vy;  // running k1 + 2 k2 + 2 k3 + k4
       chain_rhs<T, G>(px + hh * a_px, py + hh * a_py, vx + hh * a_vx, vy + hh * a_vy, cd, first,
-                      im, b_px, b_py, b_vx, b_vy);
+                      free_mass, im, b_px, b_py, b_vx, b_vy);
       s_px += T(2) * b_px; s_py += T(2) * b_py; s_vx += T(2) * b_vx; s_vy += T(2) * b_vy;
       chain_rhs<T, G>(px + hh * b_px, py + hh * b_py, vx + hh * b_vx, vy + hh * b_vy, cd, first,
-                      im, a_px, a_py, a_vx, a_vy);
+                      free_mass, im, a_px, a_py, a_vx, a_vy);
       s_px += T(2) * a_px; s_py += T(2) * a_py; s_vx += T(2) * a_vx; s_vy += T(2) * a_vy;
-      chain_rhs<T, G>(px + h * a_px, py + h * a_py, vx + h * a_vx, vy + h * a_vy, cd, first, im,
-                      b_px, b_py, b_vx, b_vy);
+      chain_rhs<T, G>(px + h * a_px, py + h * a_py, vx + h * a_vx, vy + h * a_vy, cd, first,
+                      free_mass, im, b_px, b_py, b_vx, b_vy);
       s_px += b_px; s_py += b_py; s_vx += b_vx; s_vy += b_vy;
       px += h6 * s_px;
       py += h6 * s_py;
@@ -494,7 +502,7 @@ __device__ __forceinline__ void line_select_and_apply(T* costs, int L, int n, T*
                                                       const T* __restrict__ dU,
                                                       const T* __restrict__ alpha,
                                                       T* __restrict__ Cout, double* info,
-                                                      int* jstar) {
+                                                      int32_t* status, int* jstar) {
   __syncthreads();
   if (threadIdx.x == 0) {
     int best = -1;
@@ -514,6 +522,7 @@ __device__ __forceinline__ void line_select_and_apply(T* costs, int L, int n, T*
       info[1] = best >= 0 ? static_cast<double>(bc) : __builtin_nan("");
       info[2] = static_cast<double>(best);
     }
+    if (status) *status = best >= 0 ? GNMPPI_OK : GNMPPI_ENONFINITE;
   }
   __syncthreads();
   const int b = *jstar;
@@ -527,8 +536,8 @@ template <typename T, int G>
 __device__ __forceinline__ void line_search_chain_block(
     ChainDev<T> cd, int N, const T* __restrict__ x0, const T* __restrict__ q,
     const T* __restrict__ r, const T* __restrict__ xref, T* U, const T* __restrict__ dU,
-    const T* __restrict__ alpha, int L, T* __restrict__ Cout, double* info, int stage_ctl,
-    unsigned char* ctl_raw) {
+    const T* __restrict__ alpha, int L, T* __restrict__ Cout, double* info, int32_t* status,
+    int stage_ctl, unsigned char* ctl_raw) {
   __shared__ T costs[64];
   __shared__ int jstar;
   const int j = threadIdx.x / G;
@@ -552,17 +561,18 @@ __device__ __forceinline__ void line_search_chain_block(
     c = chain_rollout<T, G, true>(cd, N, x0, q, r, xref, ctrl, sink);
   }
   if (j < L && (threadIdx.x & (G - 1)) == 0) costs[j] = c;
-  line_select_and_apply(costs, L, n, U, dU, alpha, Cout, info, &jstar);
+  line_select_and_apply(costs, L, n, U, dU, alpha, Cout, info, status, &jstar);
 }
 
 template <typename T, int G>
 __global__ void __launch_bounds__(1024) line_search_chain_kernel(
     ChainDev<T> cd, int N, const T* __restrict__ x0, const T* __restrict__ q,
     const T* __restrict__ r, const T* __restrict__ xref, T* U, const T* __restrict__ dU,
-    const T* __restrict__ alpha, int L, T* __restrict__ Cout, double* info, int stage_ctl) {
+    const T* __restrict__ alpha, int L, T* __restrict__ Cout, double* info, int32_t* status,
+    int stage_ctl) {
   extern __shared__ unsigned char ctl_raw[];
-  line_search_chain_block<T, G>(cd, N, x0, q, r, xref, U, dU, alpha, L, Cout, info, stage_ctl,
-                                ctl_raw);
+  line_search_chain_block<T, G>(cd, N, x0, q, r, xref, U, dU, alpha, L, Cout, info, status,
+                                stage_ctl, ctl_raw);
 }
 
 // Batched: item = instance; L * G threads.
@@ -576,7 +586,7 @@ __global__ void __launch_bounds__(1024) batch_line_search_kernel(const BatchInst
     ChainDev<float> cd = cd0;
     cd.M = b.M;
     line_search_chain_block<float, G>(cd, b.N, b.x0, b.q, b.r, b.xref, b.U, b.dU, b.alpha, L,
-                                      nullptr, b.info, 1, ctl_raw);
+                                      nullptr, b.info, b.status + 2, 1, ctl_raw);
     __syncthreads();
   }
 }
@@ -585,7 +595,7 @@ template <typename T, int D>
 __global__ void __launch_bounds__(64) line_search_di_kernel(
     int N, T dt, const T* __restrict__ x0, const T* __restrict__ q, const T* __restrict__ r,
     const T* __restrict__ xref, T* U, const T* __restrict__ dU, const T* __restrict__ alpha,
-    int L, T* __restrict__ Cout, double* info) {
+    int L, T* __restrict__ Cout, double* info, int32_t* status) {
   __shared__ T costs[64];
   __shared__ int jstar;
   const int j = threadIdx.x;
@@ -593,7 +603,7 @@ __global__ void __launch_bounds__(64) line_search_di_kernel(
     CtrlLine<T> ctrl{U, dU, alpha[j]};
     costs[j] = di_rollout<T, D, false>(N, dt, x0, q, r, xref, ctrl, nullptr, 0, 0, false);
   }
-  line_select_and_apply(costs, L, N * D, U, dU, alpha, Cout, info, &jstar);
+  line_select_and_apply(costs, L, N * D, U, dU, alpha, Cout, info, status, &jstar);
 }
 
 // ---- dispatch ---------------------------------------------------------------
@@ -668,7 +678,8 @@ hipError_t rollout_typed(const gnmppi_problem& p, const T* x0, const T* U, const
 
 template <typename T>
 hipError_t line_search_typed(const gnmppi_problem& p, const T* x0, T* U, const T* dU,
-                             const T* alpha, int L, T* C, double* info, hipStream_t st) {
+                             const T* alpha, int L, T* C, double* info, int32_t* status,
+                             hipStream_t st) {
   const T* q = static_cast<const T*>(p.q);
   const T* r = static_cast<const T*>(p.r);
   const T* xr = static_cast<const T*>(p.x_ref);
@@ -682,7 +693,7 @@ hipError_t line_search_typed(const gnmppi_problem& p, const T* x0, T* U, const T
 #define GNM_LS_CASE(GG)                                                                          \
   case GG:                                                                                       \
     hipLaunchKernelGGL((line_search_chain_kernel<T, GG>), dim3(1), dim3(threads), lds, st, cd,    \
-                       p.N, x0, q, r, xr, U, dU, alpha, L, C, info, stage);                      \
+                       p.N, x0, q, r, xr, U, dU, alpha, L, C, info, status, stage);              \
     break;
     switch (G) {
       GNM_LS_CASE(1)
@@ -699,7 +710,7 @@ hipError_t line_search_typed(const gnmppi_problem& p, const T* x0, T* U, const T
 #define GNM_LSD_CASE(DD)                                                                      \
   case DD:                                                                                    \
     hipLaunchKernelGGL((line_search_di_kernel<T, DD>), dim3(1), dim3(64), 0, st, p.N, dt, x0, q, \
-                       r, xr, U, dU, alpha, L, C, info);                                      \
+                       r, xr, U, dU, alpha, L, C, info, status);                              \
     break;
     switch (p.nu) {
       GNM_LSD_CASE(1)
@@ -787,16 +798,17 @@ hipError_t launch_batch_line_search(int G, const BatchInst* inst, const BatchLau
 }
 
 hipError_t launch_line_search(const gnmppi_problem& p, const void* x0, void* U, const void* dU,
-                              const void* alpha, int L, void* C, double* info, hipStream_t st) {
+                              const void* alpha, int L, void* C, double* info, int32_t* status,
+                              hipStream_t st) {
   if (p.dtype == GNMPPI_F32)
     return line_search_typed<float>(p, static_cast<const float*>(x0), static_cast<float*>(U),
                                     static_cast<const float*>(dU),
                                     static_cast<const float*>(alpha), L, static_cast<float*>(C),
-                                    info, st);
+                                    info, status, st);
   return line_search_typed<double>(p, static_cast<const double*>(x0), static_cast<double*>(U),
                                    static_cast<const double*>(dU),
                                    static_cast<const double*>(alpha), L, static_cast<double*>(C),
-                                   info, st);
+                                   info, status, st);
 }
 
 }  // namespace gnm

@@ -118,7 +118,10 @@ class GNMPPI:
         self.C_line = torch.zeros(settings.n_alpha, dtype=dt, device=dev)
         iters = max_iters if max_iters is not None else settings.iters
         self.info = torch.zeros(max(iters, 1), 3, dtype=torch.float64, device=dev)
-        self.status = torch.zeros(iters if iters else 1, 3, dtype=torch.int32, device=dev)
+        # status words per iteration: Jacobian (rank of G), GGN step (positive
+        # definiteness), G^{-1} factored on the side stream, line search (a
+        # finite candidate)
+        self.status = torch.zeros(iters if iters else 1, 4, dtype=torch.int32, device=dev)
         code = _lib.F32 if dt == torch.float32 else _lib.F64
         self.work_j = _workspace(_lib.gnmppi_jacobian_workspace(code, m, n, K), dev)
         self.works = [self.work_j]
@@ -229,7 +232,7 @@ class GNMPPI:
                              self.status[it, 1:2])
         tick.next("line_search")
         _lib.gnmppi_line_search(self.p, self.x0, self.U, self.dU, self.alpha, self.C_line,
-                                self.info[it])
+                                self.info[it], self.status[it, 3:4])
         tick.stop()
         if self.overlap and j_done is not None:
             self._side_gram(it + 1, after=j_done)

@@ -141,15 +141,17 @@ def test_other_entry_points_reject_bad_arguments():
     assert lib.gnmppi_ggn_step(_lib.F64, 120, 40, 0x100, 40, 0x200, 1, -1.0, 0x300, 0x1000, wg, None, None) == _lib.EINVAL
     assert lib.gnmppi_ggn_step(_lib.F64, 120, 40, 0x100, 40, 0x200, 1, 0.0, 0x300, 0x1000, wg - 8, None, None) == _lib.ENOSPACE
     p = _problem()
-    assert lib.gnmppi_line_search(ctypes.byref(p), 0x10, 0x20, 0x30, 0x40, 0, None, None, None) == _lib.EINVAL
-    assert lib.gnmppi_line_search(ctypes.byref(p), 0x10, 0x20, 0x30, 0x40, 65, None, None, None) == _lib.EINVAL
+    assert lib.gnmppi_line_search(ctypes.byref(p), 0x10, 0x20, 0x30, 0x40, 0, None, None, None,
+                                  None) == _lib.EINVAL
+    assert lib.gnmppi_line_search(ctypes.byref(p), 0x10, 0x20, 0x30, 0x40, 65, None, None, None,
+                                  None) == _lib.EINVAL
     assert lib.gnmppi_sigma_points(_lib.F64, 4, 1.0, 0x10, 7, None) == _lib.EINVAL
 
 
 def test_status_strings_and_version():
     assert _lib.status_string(_lib.ENOTPD) == "normal matrix not positive definite"
     assert _lib.status_string(123) == "unknown status"
-    assert _lib.gnmppi_abi_version() == 1
+    assert _lib.gnmppi_abi_version() == 2
 
 
 def test_mlp_entry_points_reject_bad_arguments():

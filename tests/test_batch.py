@@ -4,9 +4,11 @@ persistent launches per step and shape class).
 Parity: every instance of a small uneven batch -- masses 3..16 (all three
 lane-group classes), horizons 7..33 (several MFMA-tile and sweep classes),
 K 64..512 -- after one iteration against the FP64 oracle fed the same Philox
-stream (instance b uses key seed + b); after two iterations against the
-single-instance solver; graph replays against eager iterations; every tuning
-against the default one.
+stream (instance b uses key seed + b); a batch with one instance per shape
+class the 1024-instance workload runs (contraction and G-sweep classes 3..10,
+GGN-sweep classes 3..11, lane groups of 4, 8 and 16, K 512..4096) the same
+way; after two iterations against the single-instance solver; graph replays
+against eager iterations; every tuning against the default one.
 """
 import ctypes
 
@@ -15,8 +17,8 @@ import pytest
 import torch
 
 import workloads as wl
-from _parity import assert_parity, rnd, round_problem
-from oracle import philox, solvers
+from _parity import TOL, assert_parity, rnd, round_problem
+from oracle import ggn, jacobian, ocp, philox, solvers
 from paper_2512_04579_amd import _lib
 from paper_2512_04579_amd.batch import BatchGNMPPI, autotune
 from paper_2512_04579_amd.problem import DeviceProblem
@@ -55,7 +57,46 @@ def test_batch_first_iteration_matches_oracle():
                                 sigma_min=st.sigma_min)
         assert info[b, 0] == h.alpha[0], (b, info[b], h.alpha)
         assert_parity([info[b, 1]], [h.cost[0]], "f32", f"instance {b} cost")
-        assert_parity(batch.controls(b).double().cpu().numpy(), Uo, "f32", f"instance {b} U", tol=1e-3)
+        assert_parity(batch.controls(b).double().cpu().numpy(), Uo, "f32", f"instance {b} U")
+
+
+# One instance per shape class of the 1024-instance workload (M in 4..16, N in
+# 20..80, K in {512 .. 4096}): 16-column MFMA classes ceil(2N / 16) = 3..10 of
+# the contraction, the J^T J tiles and the G sweep, GGN-sweep classes
+# ceil((2N + 1) / 16) = 3..11, and lane groups of 4, 8 and 16 per sample.
+C3_SHAPES = [(4, 20, 512), (5, 28, 1024), (9, 36, 2048), (16, 44, 4096), (4, 52, 1024),
+             (5, 60, 2048), (9, 66, 4096), (16, 76, 2048), (12, 79, 512), (16, 80, 4096)]
+
+
+@pytest.mark.gpu
+def test_batch_every_c3_shape_class_matches_oracle():
+    inst = []
+    for i, (M, N, K) in enumerate(C3_SHAPES):
+        prob, x0 = wl.chain_problem(n_masses=M, N=N, dt=0.05, seed=70 + i)
+        inst.append((prob, x0, K))
+    classes = {(-(-p.n // 16), -(-(p.n + 1) // 16)) for p, _, _ in inst}
+    assert {c for c, _ in classes} == set(range(3, 11)) and {h for _, h in classes} == set(range(3, 12))
+    st = _settings()
+    batch = BatchGNMPPI(inst, st, seed=31)
+    batch.step(0)
+    torch.cuda.synchronize()
+    status, info = batch.status.cpu().numpy(), batch.info.cpu().numpy()
+    assert (status == 0).all(), status
+    sig = st.sigma0  # iteration 0
+    alphas = rnd(0.5 ** np.arange(st.n_alpha), "f32")
+    for b, (p, x0, K) in enumerate(inst):
+        rp, x0r = round_problem(p, "f32"), rnd(x0, "f32")
+        W = rnd(philox.perturbations(p.n, K, sig, 31 + b, 0, "f32"), "f32")
+        R, _ = ocp.rollout_batch(rp, x0r, np.zeros(p.n), W, nominal=True)
+        d_ref = ggn.direction(jacobian.ls(R, W), R[:, 0])
+        C_ref = ocp.cost_from_residual(ocp.residual(rp, x0r, d_ref[:, None] * alphas[None, :]))
+        j = int(info[b, 2])
+        # the device's step length is an argmin of the oracle's candidate costs
+        assert 0 <= j < st.n_alpha and info[b, 0] == alphas[j], (b, info[b])
+        assert C_ref[j] <= C_ref.min() * (1 + 10 * TOL["f32"]), (b, j, C_ref)
+        assert_parity([info[b, 1]], [C_ref[j]], "f32", f"instance {b} {C3_SHAPES[b]} cost")
+        assert_parity(batch.controls(b).double().cpu().numpy(), alphas[j] * d_ref, "f32",
+                      f"instance {b} {C3_SHAPES[b]} U")
 
 
 @pytest.mark.gpu
@@ -76,7 +117,7 @@ def test_batch_matches_the_single_instance_solver():
         assert (status == 0).all()
         assert_parity([batch.info[b, 1].item()], [costs[1]], "f32", f"instance {b} cost")
         assert_parity(batch.controls(b).double().cpu().numpy(), single.U.double().cpu().numpy(), "f32",
-                      f"instance {b} U", tol=1e-3)
+                      f"instance {b} U")
 
 
 @pytest.mark.gpu

@@ -84,3 +84,20 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(m, 0.1 * g)
     np.testing.assert_allclose(v, 0.001 * g * g)
     assert math.isclose(p1[3], 1.0)
+
+
+def test_adam_bias_correction_with_a_constant_gradient():
+    # With the same gradient g at every step, m_t = (1 - beta1^t) g and
+    # v_t = (1 - beta2^t) g^2, so the bias-corrected moments are exactly g and
+    # g^2 at every t and each step moves by lr g / (|g| + eps): after T steps
+    # p_T = p_0 - T lr g / (|g| + eps).  A correction by (1 - beta)^t, or none,
+    # agrees with this only at t = 1.
+    g = np.array([0.3, -2.0, 1e-3, 5.0])
+    p0 = np.array([1.0, -1.0, 0.5, 2.0])
+    lr, eps, T = 1e-3, 1e-8, 25
+    p, m, v = p0.copy(), np.zeros(4), np.zeros(4)
+    for t in range(1, T + 1):
+        p, m, v = mlp.adam(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=eps)
+        np.testing.assert_allclose(p, p0 - t * lr * g / (np.abs(g) + eps), rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(m, (1 - 0.9 ** T) * g, rtol=1e-12)
+    np.testing.assert_allclose(v, (1 - 0.999 ** T) * g * g, rtol=1e-12)

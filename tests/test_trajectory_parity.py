@@ -1,0 +1,69 @@
+"""Step-wise parity of Alg. 1 along the GPU's own trajectory on the c2 chain
+(16 masses, N=50, K=4096, float32, BF16x3 sample contraction), for all 50
+iterations.
+
+At iteration k the oracle is fed exactly what the device used: the iterate
+U_k and the perturbations W_k the device sampler drew (Philox stream k).  It
+then recomputes, in FP64, the GGN direction of Eqs. (10) and (13) and the L
+candidate costs C(U_k + gamma^j Delta) of Eq. (15) along the device's
+direction.  The device's direction and costs must match at the float32 bar,
+the device's step length must be a valid argmin under the oracle's costs,
+and U_{k+1} must be U_k + alpha* Delta.
+
+Tolerance of the direction: normwise relative 1e-4 against
+max(||Delta_ref||, 1e-3 ||U_k||) -- the iterate's own scale bounds the
+absolute error once the direction itself is small (the applied update is
+U_k + alpha Delta, so that is the error the trajectory carries).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from _parity import TOL, host, rnd, round_problem
+from oracle import ggn, jacobian, ocp
+from paper_2512_04579_amd.problem import DeviceProblem
+from paper_2512_04579_amd.solver import GNMPPI
+
+pytestmark = pytest.mark.gpu
+
+
+def test_c2_every_iteration_matches_the_oracle_along_the_device_trajectory():
+    w = wl.c2()
+    p, st = w.problem, w.settings
+    rp, x0r = round_problem(p, "f32"), rnd(w.x0, "f32")
+    solver = GNMPPI(DeviceProblem(p, "f32"), w.x0, st, seed=1, max_iters=st.iters)
+    K = solver.K
+    alphas = rnd(ggn.step_lengths(st.gamma, st.n_alpha), "f32")
+    costfun = lambda Ub: ocp.cost_from_residual(ocp.residual(rp, x0r, Ub))  # noqa: E731
+    worst = {"delta": 0.0, "costs": 0.0}
+    for it in range(st.iters):
+        Uk = host(solver.U)
+        solver.step(it)
+        torch.cuda.synchronize()
+        Wk = host(solver.W[:, :K])
+        d_dev, C_dev = host(solver.dU), host(solver.C_line)
+        info = host(solver.info[it])
+        U_next = host(solver.U)
+        # the oracle on the device's inputs
+        R, _ = ocp.rollout_batch(rp, x0r, Uk, Wk, nominal=True)
+        d_ref = ggn.direction(jacobian.ls(R, Wk), R[:, 0])
+        scale = max(np.linalg.norm(d_ref), 1e-3 * np.linalg.norm(Uk))
+        e_d = np.linalg.norm(d_dev - d_ref) / scale
+        cand = rnd(Uk[:, None] + d_dev[:, None] * alphas[None, :], "f32")
+        C_ref = costfun(cand)
+        e_c = np.linalg.norm(C_dev - C_ref) / np.linalg.norm(C_ref)
+        worst["delta"] = max(worst["delta"], e_d)
+        worst["costs"] = max(worst["costs"], e_c)
+        print(f"iteration {it}: |Delta| {np.linalg.norm(d_ref):.3e} err {e_d:.2e}; "
+              f"costs err {e_c:.2e}; alpha {info[0]:.3g} C {info[1]:.6g}", flush=True)
+        assert e_d <= TOL["f32"], f"iteration {it}: direction error {e_d:.3e}"
+        assert e_c <= TOL["f32"], f"iteration {it}: candidate cost error {e_c:.3e}"
+        assert np.abs(C_dev - C_ref).max() <= TOL["f32"] * np.abs(C_ref).max()
+        j = int(info[2])
+        assert 0 <= j < st.n_alpha and info[0] == alphas[j] and info[1] == C_dev[j]
+        assert C_ref[j] <= C_ref.min() * (1 + 10 * TOL["f32"]), (it, j, C_ref)
+        np.testing.assert_array_equal(U_next, rnd(Uk + alphas[j] * d_dev, "f32"))
+    assert (solver.history(st.iters)[2] == 0).all()
+    print(f"worst over {st.iters} iterations: direction {worst['delta']:.2e}, "
+          f"candidate costs {worst['costs']:.2e}")
