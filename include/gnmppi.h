@@ -215,6 +215,23 @@ int gnmppi_ggn_step(int32_t dtype, int32_t m, int32_t n, const void *J,
                     double lm_lambda, void *dU, void *work, size_t work_bytes,
                     int32_t *status, void *stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture that may not call hipMalloc, tight serving loops, harnesses that
+ * forbid allocation: gnmppi_ggn_step with no `work` argument.  Its scratch
+ * (the J^T J chunk partials and the reduced normal matrix) is an 8 MiB array
+ * in device memory defined by the library; each GPU the library runs on
+ * holds its own copy until the process ends.  The call allocates nothing.
+ * Sizes with gnmppi_ggn_workspace(dtype, m, n) > 8388608 bytes (8 MiB; e.g.
+ * n = 100 allows m up to 25856, n = 192 up to 6912) return
+ * GNMPPI_ENOSPACE and enqueue nothing.  Every call on one GPU uses that GPU's
+ * one array, so calls that overlap in time on one GPU (different streams or
+ * threads) race: the caller must order them.  Arguments, results and the
+ * status word are those of gnmppi_ggn_step. */
+int gnmppi_ggn_step_noalloc(int32_t dtype, int32_t m, int32_t n, const void *J,
+                            int64_t ldj, const void *r0, int64_t inc_r0,
+                            double lm_lambda, void *dU, int32_t *status,
+                            void *stream);
+
 /* ---- a6: parallel line search and update (Eqs. (14), (15); Alg. 1) ------
  * Rolls out the L candidates U + alpha[j] dU in one launch (costs only),
  * picks j* = the first index of the smallest finite cost, and applies

@@ -85,6 +85,8 @@ SIGNATURES = {
     "gnmppi_ggn_workspace": (c_size_t, [c_int32, c_int32, c_int32]),
     "gnmppi_ggn_step": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_int64, c_void_p, c_int64,
                                   c_double, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
+    "gnmppi_ggn_step_noalloc": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_int64, c_void_p,
+                                          c_int64, c_double, c_void_p, c_void_p, c_void_p]),
     "gnmppi_line_search": (c_int32, [PROBLEM_P, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
                                      c_void_p, c_void_p, c_void_p, c_void_p]),
     "gnmppi_batch_workspace": (c_size_t, [PROBLEM_P, c_int32, BATCH_P, BSET_P, BTUNE_P]),
@@ -235,6 +237,14 @@ def gnmppi_ggn_step(J, r0, lm_lambda: float, dU, work, status=None, inc_r0: int 
     _check("gnmppi_ggn_step", load().gnmppi_ggn_step(
         _dtype_code(J), m, n, _ptr(J), _ld(J), _ptr(r0), int(inc_r0), float(lm_lambda), _ptr(dU),
         _ptr(work), work.numel() * work.element_size(), _ptr(status), _stream(stream)))
+
+
+def gnmppi_ggn_step_noalloc(J, r0, lm_lambda: float, dU, status=None, inc_r0: int = 1,
+                            stream=None):
+    m, n = J.shape
+    _check("gnmppi_ggn_step_noalloc", load().gnmppi_ggn_step_noalloc(
+        _dtype_code(J), m, n, _ptr(J), _ld(J), _ptr(r0), int(inc_r0), float(lm_lambda), _ptr(dU),
+        _ptr(status), _stream(stream)))
 
 
 def gnmppi_line_search(problem, x0, U, dU, alpha, C=None, info=None, status=None, stream=None):

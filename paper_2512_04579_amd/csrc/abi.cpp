@@ -149,6 +149,18 @@ int gnmppi_ggn_step(int32_t dtype, int32_t m, int32_t n, const void* J, int64_t 
                                    as_stream(stream)));
 }
 
+int gnmppi_ggn_step_noalloc(int32_t dtype, int32_t m, int32_t n, const void* J, int64_t ldj,
+                            const void* r0, int64_t inc_r0, double lm_lambda, void* dU,
+                            int32_t* status, void* stream) {
+  if (!dtype_ok(dtype) || m < 1 || n < 1 || n > 192) return GNMPPI_EINVAL;
+  if (J == nullptr || r0 == nullptr || dU == nullptr) return GNMPPI_EINVAL;
+  if (ldj < n || inc_r0 < 1 || !(lm_lambda >= 0.0) || !std::isfinite(lm_lambda))
+    return GNMPPI_EINVAL;
+  if (gnm::ggn_plan(dtype, m, n).total > gnm::ggn_noalloc_capacity()) return GNMPPI_ENOSPACE;
+  return status_of(gnm::launch_ggn_noalloc(dtype, m, n, J, ldj, r0, inc_r0, lm_lambda, dU, status,
+                                           as_stream(stream)));
+}
+
 int gnmppi_line_search(const gnmppi_problem* p, const void* x0, void* U, const void* dU,
                        const void* alpha, int32_t L, void* C, double* info, int32_t* status,
                        void* stream) {

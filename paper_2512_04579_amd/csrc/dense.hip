@@ -25,6 +25,7 @@
 //      [J r0]^T [J r0] over a chunk of rows with the 16x16x4 f64 MFMA
 //      (products of float inputs are exact in double); one partial sum per
 //      chunk.
+#include <mutex>
 #include <type_traits>
 
 #include "batch.hpp"
@@ -510,6 +511,56 @@ hipError_t launch_ggn(int dtype, int m, int n, const void* J, int64_t ldj, const
                                status, GNMPPI_ENOTPD, st);
   return launch_sweep(g.P, n, kSweepDirection, Hsum, nullptr, 0, static_cast<double*>(dU),
                               status, GNMPPI_ENOTPD, st);
+}
+
+// ---- the GGN step without a caller workspace ----------------------------------
+
+// Scratch of gnmppi_ggn_step_noalloc: the [J r0]^T [J r0] chunk partials and
+// the reduced normal matrix, in a file-scope device array (each GPU holds its
+// own copy for the life of the process).  In host code `scratch` names a
+// host-side stand-in, never the device memory: its device address comes from
+// hipGetSymbolAddress, looked up once per device and kept in kScratchPtr.
+constexpr size_t kNoAllocScratchBytes = size_t{8} << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex kScratchMutex;
+void* kScratchPtr[kMaxDevices] = {};
+}  // namespace
+
+size_t ggn_noalloc_capacity() { return kNoAllocScratchBytes; }
+
+// The current device's address of `scratch` (looked up on the first call on
+// that device, with it current).
+static hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(kScratchMutex);
+  if (kScratchPtr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr || (reinterpret_cast<uintptr_t>(p) & 255u) != 0) return hipErrorInvalidSymbol;
+    kScratchPtr[dev] = p;
+  }
+  *out = kScratchPtr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_ggn_noalloc(int dtype, int m, int n, const void* J, int64_t ldj, const void* r0,
+                              int64_t inc_r0, double lm_lambda, void* dU, int32_t* status,
+                              hipStream_t st) {
+  if (ggn_plan(dtype, m, n).total > kNoAllocScratchBytes) return hipErrorInvalidValue;
+  void* work = nullptr;
+  const hipError_t e = scratch_address(&work);
+  if (e != hipSuccess) return e;
+  // every element the step reads from its workspace is written earlier in
+  // the same step (all chunk partials, both triangles of the normal
+  // matrix), so nothing needs clearing between calls
+  return launch_ggn(dtype, m, n, J, ldj, r0, inc_r0, lm_lambda, dU, work, status, st);
 }
 
 // ---- batched launchers ------------------------------------------------------

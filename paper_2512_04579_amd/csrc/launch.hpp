@@ -118,6 +118,14 @@ hipError_t launch_ggn(int dtype, int m, int n, const void* J, int64_t ldj, const
                       int64_t inc_r0, double lm_lambda, void* dU, void* work,
                       int32_t* status, hipStream_t st);
 
+// The GGN step with its scratch in the library's fixed device array (no
+// workspace argument, no allocation); sizes whose ggn_plan total exceeds
+// ggn_noalloc_capacity() are rejected with hipErrorInvalidValue.
+size_t ggn_noalloc_capacity();
+hipError_t launch_ggn_noalloc(int dtype, int m, int n, const void* J, int64_t ldj, const void* r0,
+                              int64_t inc_r0, double lm_lambda, void* dU, int32_t* status,
+                              hipStream_t st);
+
 // Batched iteration steps (batch.hpp); each launcher covers one shape class.
 struct BatchInst;
 struct BatchLaunch;

@@ -168,3 +168,15 @@ def test_mlp_entry_points_reject_bad_arguments():
                                    None) == _lib.EINVAL
     assert lib.gnmppi_mlp_adam(10, 0x10, 0x20, 0x30, 0x40, 0x50, 1e-3, 0.9, 0.999, 1e-8, 0, None) == _lib.EINVAL
     assert lib.gnmppi_mlp_adam(10, 0x10, 0x20, 0x30, 0x40, 0x50, 1e-3, 1.0, 0.999, 1e-8, 1, None) == _lib.EINVAL
+
+
+def test_noalloc_ggn_step_rejects_without_touching_a_device():
+    lib = _lib.load()
+    # gnmppi_ggn_workspace(F32, 6913, 192) exceeds the 8 MiB scratch
+    assert _lib.gnmppi_ggn_workspace(_lib.F32, 6913, 192) > 8 << 20
+    assert _lib.gnmppi_ggn_workspace(_lib.F32, 6912, 192) <= 8 << 20
+    args = (0x1000, 192, 0x2000, 1, 0.0, 0x3000, None, None)
+    assert lib.gnmppi_ggn_step_noalloc(_lib.F32, 6913, 192, *args) == _lib.ENOSPACE
+    assert lib.gnmppi_ggn_step_noalloc(_lib.F32, 6913, 193, *args) == _lib.EINVAL
+    assert lib.gnmppi_ggn_step_noalloc(_lib.F32, 100, 50, None, 50, 0x2000, 1, 0.0, 0x3000, None,
+                                       None) == _lib.EINVAL
