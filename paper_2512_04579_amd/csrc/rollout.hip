@@ -138,37 +138,67 @@ struct NoSink {
   __device__ __forceinline__ void step(int, int, bool, bool, T, T, T, T, T, T) {}
 };
 
-// StagedSink collects the residual rows of the block's samples in an LDS
-// tile (double-buffered; step j of a flush occupies rows j (4 M + 2) ..,
-// so the tile's rows are consecutive rows of R) and every F steps (and at
-// the last step) stores them as contiguous row segments of the
-// sample-fastest R (or into r0 for the nominal column), four samples per
-// store.  Column K (the nominal) and the columns left of it in a partial
-// last chunk go one row per thread; the threads that store column K also
-// sum its squares, so the nominal cost needs no cost terms in the rollout
-// itself.  One barrier per F steps; all threads of the block must call it.
+// Stores the first nfr rows of one residual tile t (rows base .. base + nfr
+// of R, the columns col0 .. col0 + kSpb of the block) as contiguous row
+// segments of the sample-fastest R (or into r0 for the nominal column K),
+// four samples per store; tid in [0, kBlock) numbers the storing threads.
+// Column K and the columns left of it in a partial last chunk go one row per
+// thread; the threads that store column K also add its squares to csum, so
+// the nominal cost needs no cost terms in the rollout itself.
+template <typename T, int kSpb>
+__device__ __forceinline__ void drain_tile(const T (*t)[kSpb + 1], int nfr, int64_t base, int tid,
+                                           T* __restrict__ R, int64_t ldr, T* __restrict__ r0,
+                                           int K, int col0, bool vec, T& csum) {
+  constexpr int kVec = 4;                 // samples per vector store
+  constexpr int kChunks = kSpb / kVec;    // vector stores per row
+  static_assert(kSpb % kVec == 0 && kBlock % kChunks == 0, "chunking of a row");
+  if (vec) {
+    // whole 4-sample chunks left of column K: one vector store each
+    using V = T __attribute__((ext_vector_type(kVec)));
+    const int nvec = min(kChunks, max(0, (K - col0) / kVec));  // uniform
+    for (int idx = tid; idx < nfr * kChunks; idx += kBlock) {
+      const int fr = idx / kChunks, ch = idx % kChunks, sv = ch * kVec;
+      if (ch < nvec)
+        *reinterpret_cast<V*>(R + (base + fr) * ldr + col0 + sv) =
+            V{t[fr][sv], t[fr][sv + 1], t[fr][sv + 2], t[fr][sv + 3]};
+    }
+    // the block that holds column K: its last R columns one row per thread
+    // (the bounds are uniform, so the stores need no divergent branches)
+    const int ctail = col0 + nvec * kVec, cend = min(col0 + kSpb, K);
+    if (ctail < cend)
+      for (int fr = tid; fr < nfr; fr += kBlock)
+        for (int c = ctail; c < cend; ++c) R[(base + fr) * ldr + c] = t[fr][c - col0];
+  } else if (R) {
+    for (int idx = tid; idx < nfr * kSpb; idx += kBlock) {
+      const int fr = idx / kSpb, sc = idx % kSpb;
+      if (col0 + sc < K) R[(base + fr) * ldr + col0 + sc] = t[fr][sc];
+    }
+  }
+  // the nominal column, one row per thread whatever the layout of R (so c0
+  // sums the same terms in the same order)
+  if (col0 <= K && K < col0 + kSpb) {
+    for (int fr = tid; fr < nfr; fr += kBlock) {
+      const T v = t[fr][K - col0];
+      if (r0) r0[base + fr] = v;
+      csum += v * v;
+    }
+  }
+}
+
+// Residual tile of the block's samples in LDS, double-buffered: step j of a
+// flush occupies rows j (4 M + 2) .., so the tile's rows are consecutive rows
+// of R.  Row stride kSpb + 1: the G lanes of a sample write rows 2i of one
+// column, which a stride of kSpb would put in a single LDS bank.
 template <typename T, int G, int F>
-struct StagedSink {
+struct ResidualTile {
   static constexpr int kSpb = kBlock / G;        // samples per block
   static constexpr int kRows = 4 * G + 2;        // >= rows per step (4 M + 2)
-  // row stride kSpb + 1: the G lanes of a sample write rows 2i of one column,
-  // which a stride of kSpb would put in a single LDS bank
   static constexpr int kLd = kSpb + 1;
-  static constexpr int kVec = 4;                 // samples per vector store
-  static constexpr int kChunks = kSpb / kVec;    // vector stores per row
-  static_assert(kSpb % kVec == 0 && kBlock % kChunks == 0, "chunking of a row");
-  T (*tile)[F * kRows][kLd];                     // [2][F kRows][kLd] in LDS
-  T* R;
-  int64_t ldr;
-  T* r0;
-  int K, col0, M, grp, N;
-  bool vec;    // rows of R start 4-element aligned (uniform)
-  T csum = 0;  // this thread's share of ||r||^2 of column K (the nominal)
-  __device__ __forceinline__ void step(int k, int i, bool has_mass, bool first, T e0, T e1, T e2,
-                                       T e3, T f0, T f1) {
+  using Buf = T[F * kRows][kLd];
+  __device__ __forceinline__ static void put(Buf& b, int k, int M, int i, int grp, bool has_mass,
+                                             bool first, T e0, T e1, T e2, T e3, T f0, T f1) {
     const int rows = 4 * M + 2;
-    const int buf = (k / F) & 1, j = k % F;
-    T (*t)[kLd] = tile[buf] + j * rows;
+    T (*t)[kLd] = b + (k % F) * rows;
     if (has_mass) {
       t[2 * i][grp] = e0;
       t[2 * i + 1][grp] = e1;
@@ -179,44 +209,49 @@ struct StagedSink {
       t[4 * M][grp] = f0;
       t[4 * M + 1][grp] = f1;
     }
+  }
+};
+
+// StagedSink: the rollout threads write each step's rows into the tile and
+// every F steps (and at the last step) store them themselves after a
+// barrier (all threads of the block must call it).
+template <typename T, int G, int F>
+struct StagedSink {
+  using Tile = ResidualTile<T, G, F>;
+  static constexpr int kSpb = Tile::kSpb;
+  static constexpr int kRows = Tile::kRows;
+  static constexpr int kLd = Tile::kLd;
+  T (*tile)[F * kRows][kLd];                     // [2][F kRows][kLd] in LDS
+  T* R;
+  int64_t ldr;
+  T* r0;
+  int K, col0, M, grp, N;
+  bool vec;    // rows of R start 4-element aligned (uniform)
+  T csum = 0;  // this thread's share of ||r||^2 of column K (the nominal)
+  __device__ __forceinline__ void step(int k, int i, bool has_mass, bool first, T e0, T e1, T e2,
+                                       T e3, T f0, T f1) {
+    const int buf = (k / F) & 1, j = k % F;
+    Tile::put(tile[buf], k, M, i, grp, has_mass, first, e0, e1, e2, e3, f0, f1);
     if (j != F - 1 && k != N - 1) return;  // uniform: flush every F steps and at the end
     __syncthreads();
-    // tile row fr is row (k - j) rows + fr of R
-    const int64_t base = static_cast<int64_t>(k - j) * rows;
-    const int nfr = (j + 1) * rows;
-    if (vec) {
-      // whole 4-sample chunks left of column K: one vector store each
-      using V = T __attribute__((ext_vector_type(kVec)));
-      const int nvec = min(kChunks, max(0, (K - col0) / kVec));  // uniform
-      for (int idx = threadIdx.x; idx < nfr * kChunks; idx += kBlock) {
-        const int fr = idx / kChunks, ch = idx % kChunks, sv = ch * kVec;
-        if (ch < nvec)
-          *reinterpret_cast<V*>(R + (base + fr) * ldr + col0 + sv) =
-              V{tile[buf][fr][sv], tile[buf][fr][sv + 1], tile[buf][fr][sv + 2],
-                tile[buf][fr][sv + 3]};
-      }
-      // the block that holds column K: its last R columns one row per
-      // thread (the bounds are uniform, so the stores need no divergent
-      // branches)
-      const int ctail = col0 + nvec * kVec, cend = min(col0 + kSpb, K);
-      if (ctail < cend)
-        for (int fr = threadIdx.x; fr < nfr; fr += kBlock)
-          for (int c = ctail; c < cend; ++c) R[(base + fr) * ldr + c] = tile[buf][fr][c - col0];
-    } else if (R) {
-      for (int idx = threadIdx.x; idx < nfr * kSpb; idx += kBlock) {
-        const int fr = idx / kSpb, sc = idx % kSpb;
-        if (col0 + sc < K) R[(base + fr) * ldr + col0 + sc] = tile[buf][fr][sc];
-      }
-    }
-    // the nominal column, one row per thread whatever the layout of R (so
-    // c0 sums the same terms in the same order)
-    if (col0 <= K && K < col0 + kSpb) {
-      for (int fr = threadIdx.x; fr < nfr; fr += kBlock) {
-        const T v = tile[buf][fr][K - col0];
-        if (r0) r0[base + fr] = v;
-        csum += v * v;
-      }
-    }
+    const int rows = 4 * M + 2;
+    drain_tile<T, kSpb>(tile[buf], (j + 1) * rows, static_cast<int64_t>(k - j) * rows,
+                        threadIdx.x, R, ldr, r0, K, col0, vec, csum);
+  }
+};
+
+// TileSink: the rollout threads of a split block only fill the tile; at
+// every F-th step (and the last) they meet the storing waves at a barrier
+// and go on with the other buffer while those drain this one.
+template <typename T, int G, int F>
+struct TileSink {
+  using Tile = ResidualTile<T, G, F>;
+  T (*tile)[F * Tile::kRows][Tile::kLd];
+  int M, grp, N;
+  __device__ __forceinline__ void step(int k, int i, bool has_mass, bool first, T e0, T e1, T e2,
+                                       T e3, T f0, T f1) {
+    Tile::put(tile[(k / F) & 1], k, M, i, grp, has_mass, first, e0, e1, e2, e3, f0, f1);
+    if (k % F == F - 1 || k == N - 1) __syncthreads();  // uniform
   }
 };
 
@@ -298,11 +333,11 @@ __device__ __forceinline__ T chain_rollout(const ChainDev<T>& cd, int N,
   return T(0.5) * cost;
 }
 
-// out[0] = (sum of v over the block) / 2, in a fixed order; all threads of
-// the block must call it.
-template <typename T>
+// out[0] = (sum of v over the block of THREADS threads) / 2, in a fixed
+// order; all threads of the block must call it.
+template <typename T, int THREADS = kBlock>
 __device__ __forceinline__ void block_half_sum(T v, T* out) {
-  __shared__ T part[kBlock / kWave];
+  __shared__ T part[THREADS / kWave];
 #pragma unroll
   for (int off = kWave / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
   if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = v;
@@ -310,7 +345,7 @@ __device__ __forceinline__ void block_half_sum(T v, T* out) {
   if (threadIdx.x == 0) {
     T t = 0;
 #pragma unroll
-    for (int w = 0; w < kBlock / kWave; ++w) t += part[w];
+    for (int w = 0; w < THREADS / kWave; ++w) t += part[w];
     out[0] = T(0.5) * t;
   }
 }
@@ -405,6 +440,70 @@ __global__ void __launch_bounds__(256) rollout_chain_kernel(
   rollout_chain_block<T, G, staged_flush_steps<T, G>()>(cd, N, x0, q, r, xref, U, W, ldw, K, R,
                                                         ldr, C, r0, c0, nblocks, stage_ctl,
                                                         xcd_logical_block(), ctl_raw);
+}
+
+// Steps per flush of the split rollout: about 36 KB of LDS per buffer.
+template <typename T, int G>
+constexpr int split_flush_steps() {
+  constexpr int per_step = (4 * G + 2) * (kBlock / G + 1) * static_cast<int>(sizeof(T));
+  constexpr int f = 36864 / per_step;
+  return f < 1 ? 1 : (f > 8 ? 8 : f);
+}
+
+// Single instance with residuals stored: 2 kBlock threads per block.  Waves
+// 0-3 roll out the block's kSpb samples (as rollout_chain_kernel) and only
+// fill the double-buffered residual tile in LDS; waves 4-7 drain each
+// completed buffer to HBM while the rollout waves fill the other one.  At
+// one rollout wave per SIMD a store that waits for the memory queue would
+// hold up the RK4 steps of its SIMD; here it holds only a storing wave.
+// Controls are staged in LDS (dynamic shared memory).
+template <typename T, int G, int F>
+__global__ void __launch_bounds__(2 * kBlock) rollout_chain_split_kernel(
+    ChainDev<T> cd, int N, const T* __restrict__ x0, const T* __restrict__ q,
+    const T* __restrict__ r, const T* __restrict__ xref, const T* __restrict__ U,
+    const T* __restrict__ W, int64_t ldw, int K, T* __restrict__ R, int64_t ldr,
+    T* __restrict__ C, T* __restrict__ r0, T* __restrict__ c0, int nblocks) {
+  using Tile = ResidualTile<T, G, F>;
+  constexpr int kSpb = Tile::kSpb;
+  __shared__ T tile[2][F * Tile::kRows][Tile::kLd];
+  extern __shared__ unsigned char ctl_raw[];
+  const int g = xcd_logical_block();
+  if (g >= nblocks) return;  // whole padding block: no barrier is shared with it
+  const int col0 = g * kSpb;
+  const int n = 2 * N;
+  T* ctl = reinterpret_cast<T*>(ctl_raw);
+  for (int e = threadIdx.x; e < n * kSpb; e += 2 * kBlock) {
+    const int idx = e / kSpb, sl = e % kSpb, c = col0 + sl;
+    T u = U[idx];
+    if (W != nullptr && c < K) u += W[idx * ldw + c];
+    ctl[e] = u;
+  }
+  __syncthreads();
+  const bool has_nominal = c0 != nullptr && col0 <= K && K < col0 + kSpb;  // uniform
+  T csum = 0;
+  if (threadIdx.x < kBlock) {  // rollout waves (uniform per wave)
+    const int grp = threadIdx.x / G;
+    const int gcol = col0 + grp;
+    TileSink<T, G, F> sink{tile, cd.M, grp, N};
+    const CtrlStaged<T> ctrl{ctl, kSpb, grp};
+    if (C != nullptr) {
+      const T c = chain_rollout<T, G, true>(cd, N, x0, q, r, xref, ctrl, sink);
+      if (gcol < K && (threadIdx.x & (G - 1)) == 0) C[gcol] = c;
+    } else {
+      chain_rollout<T, G, false>(cd, N, x0, q, r, xref, ctrl, sink);
+    }
+  } else {  // storing waves: one drain per barrier of the rollout waves
+    const bool vec = R != nullptr && ldr % 4 == 0 &&
+                     reinterpret_cast<uintptr_t>(R) % (4 * sizeof(T)) == 0;
+    const int rows = 4 * cd.M + 2;
+    for (int k0 = 0; k0 < N; k0 += F) {
+      __syncthreads();
+      drain_tile<T, kSpb>(tile[(k0 / F) & 1], min(F, N - k0) * rows,
+                          static_cast<int64_t>(k0) * rows, threadIdx.x - kBlock, R, ldr, r0, K,
+                          col0, vec, csum);
+    }
+  }
+  if (has_nominal) block_half_sum<T, 2 * kBlock>(csum, c0);
 }
 
 // Batched: item = (instance, logical block); controls always staged.  Fewer
@@ -640,10 +739,18 @@ hipError_t rollout_typed(const gnmppi_problem& p, const T* x0, const T* U, const
     const size_t ctl_bytes = static_cast<size_t>(p.N) * 2 * (256 / G) * sizeof(T);
     const int stage = ctl_bytes <= kMaxStagedCtlBytes;
     const size_t lds = stage ? ctl_bytes : 0;
+    // residuals with staged controls: the split kernel (rollout and storing
+    // waves); costs only: the plain one
+    const bool split = stage && (R != nullptr || r0 != nullptr);
 #define GNM_CHAIN_CASE(GG)                                                                      \
   case GG:                                                                                      \
-    hipLaunchKernelGGL((rollout_chain_kernel<T, GG>), grid, dim3(256), lds, st, cd, p.N, x0, q, \
-                       r, xr, U, W, ldw, K, R, ldr, C, r0, c0, nblocks, stage);                 \
+    if (split)                                                                                  \
+      hipLaunchKernelGGL((rollout_chain_split_kernel<T, GG, split_flush_steps<T, GG>()>), grid, \
+                         dim3(2 * kBlock), lds, st, cd, p.N, x0, q, r, xr, U, W, ldw, K, R, ldr, \
+                         C, r0, c0, nblocks);                                                   \
+    else                                                                                        \
+      hipLaunchKernelGGL((rollout_chain_kernel<T, GG>), grid, dim3(kBlock), lds, st, cd, p.N,   \
+                         x0, q, r, xr, U, W, ldw, K, R, ldr, C, r0, c0, nblocks, stage);        \
     break;
     switch (G) {
       GNM_CHAIN_CASE(1)
