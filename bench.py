@@ -223,59 +223,21 @@ def bench_sweep(args):
             "timed_with": "HIP graph replays of 50 iterations per point", "sweep": rows}
 
 
-def bench_batched(args, steps: int, warmup: int, tune: bool):
-    """The batched form: ``--batch-count`` chain instances with M in 4..16,
-    N in 20..80 and K in {512, 1024, 2048, 4096} (seeded), one GN-MPPI
-    iteration for all of them per step, timed as HIP-graph replays after the
-    launch-shape autotuner has picked its tuning."""
+def batched_time_to_gap(args, inst, st, tuning):
+    """Time to a 1e-3 gap from U = 0 for the batched form, judged on the
+    seeded sample of instances whose C* the oracle computed (Method A, FP64):
+    the batch solves all of them, the clock runs until every judged instance
+    is within the gap.  Beside it, the same instances one at a time (GN-MPPI
+    and plain MPPI)."""
     import numpy as np
     import torch
 
-    import workloads as wl
-    from paper_2512_04579_amd.batch import BatchGNMPPI, autotune
+    from paper_2512_04579_amd.batch import BatchGNMPPI
 
-    inst = wl.batch_instances(args.batch_count, seed=0)
-    st = wl.c2().settings
-    L = st.n_alpha
-    batch = BatchGNMPPI(inst, st, seed=1)
-    tuned = autotune(batch, cache=None, log=progress) if tune else {
-        "tuning": "library default (an autotuner pick for this batch)"}
-    chunk = max(1, min(steps, 10))
-    reps = max(1, steps // chunk)
-    steps = reps * chunk
-    graph = batch.capture(chunk)
-    for _ in range(max(1, warmup // chunk)):
-        graph.replay()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        graph.replay()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    status = batch.status.cpu().numpy()
-    assert (status == 0).all(), f"device status words: {np.unique(status)}"
-    Ks = np.array([K for _, _, K in inst])
-    Ns = np.array([p.N for p, _, _ in inst])
-    ms_ = np.array([p.m for p, _, _ in inst])
-    ns = np.array([p.n for p, _, _ in inst])
-    sample_steps = float(((Ks + 1 + L) * Ns).sum())
-    # algorithmic HBM bytes of one iteration: R written by the rollout and read
-    # by the sample contraction, W written by the sampler and read twice
-    r_bytes = float((ms_ * Ks * 4).sum())
-    w_bytes = float((ns * Ks * 4).sum())
-    iter_bytes = 2 * r_bytes + 3 * w_bytes
-    gbps = iter_bytes / (ms * 1e-3) / 1e9
-
-    # time to a 1e-3 gap from U = 0, judged on the seeded sample of instances
-    # whose C* the oracle computed (Method A, FP64); the batch solves all of
-    # them, the clock runs until every judged instance is within the gap
-    del graph
     ref = reference_c3(inst)
     judged = np.array([r["index"] for r in ref])
     best = np.array([r["cstar"] for r in ref])
-    run = BatchGNMPPI(inst, st, seed=1, tuning=batch.tuning)
+    run = BatchGNMPPI(inst, st, seed=1, tuning=tuning)
     graphs = [run.capture(1, it0=it) for it in range(8)]  # one graph per iteration
     torch.cuda.synchronize()
     evs = [torch.cuda.Event(enable_timing=True)]
@@ -350,6 +312,62 @@ def bench_batched(args, steps: int, warmup: int, tune: bool):
         "plain_mppi_reached": f"{reached_mp}/{len(pick)} within {args.mppi_iters} iterations "
                               f"(c2's plain-MPPI temperature and sigma schedule)",
     }
+    return {"all_judged_instances": t_all, "gap_threshold": 1e-3,
+            "one_instance_at_a_time": sequential,
+            "median_gap_per_iter": [float(np.median(g)) for g in gaps],
+            "max_gap_per_iter": [float(np.max(g)) for g in gaps],
+            "cstar": f"oracle Method A (FP64) on {len(judged)} seeded instances "
+                     "(tests/golden/c3_reference_optima.json)",
+            "judged_instances": [int(b) for b in judged]}
+
+
+def bench_batched(args, steps: int, warmup: int, tune: bool):
+    """The batched form: ``--batch-count`` chain instances with M in 4..16,
+    N in 20..80 and K in {512, 1024, 2048, 4096} (seeded), one GN-MPPI
+    iteration for all of them per step, timed as HIP-graph replays after the
+    launch-shape autotuner has picked its tuning."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_2512_04579_amd.batch import BatchGNMPPI, autotune
+
+    inst = wl.batch_instances(args.batch_count, seed=0)
+    st = wl.c2().settings
+    L = st.n_alpha
+    batch = BatchGNMPPI(inst, st, seed=1, tuning=json.loads(args.batch_tuning or "{}"))
+    tuned = autotune(batch, cache=None, log=progress) if tune else {
+        "tuning": args.batch_tuning or "library default (an autotuner pick for this batch)"}
+    chunk = max(1, min(steps, 10))
+    reps = max(1, steps // chunk)
+    steps = reps * chunk
+    graph = batch.capture(chunk)
+    for _ in range(max(1, warmup // chunk)):
+        graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    status = batch.status.cpu().numpy()
+    assert (status == 0).all(), f"device status words: {np.unique(status)}"
+    Ks = np.array([K for _, _, K in inst])
+    Ns = np.array([p.N for p, _, _ in inst])
+    ms_ = np.array([p.m for p, _, _ in inst])
+    ns = np.array([p.n for p, _, _ in inst])
+    sample_steps = float(((Ks + 1 + L) * Ns).sum())
+    # algorithmic HBM bytes of one iteration: R written by the rollout and read
+    # by the sample contraction, W written by the sampler and read twice
+    r_bytes = float((ms_ * Ks * 4).sum())
+    w_bytes = float((ns * Ks * 4).sum())
+    iter_bytes = 2 * r_bytes + 3 * w_bytes
+    gbps = iter_bytes / (ms * 1e-3) / 1e9
+
+    del graph
+    ttg = batched_time_to_gap(args, inst, st, batch.tuning) if not args.no_time_to_gap else None
     return {
         "metric": METRIC,
         "value": 1e3 / ms,
@@ -368,13 +386,7 @@ def bench_batched(args, steps: int, warmup: int, tune: bool):
                      "peak": PEAK["hbm_GBps"], "unit": "GB/s", "frac": gbps / PEAK["hbm_GBps"],
                      "traffic": None, "algorithmic_bytes": iter_bytes},
         "autotune": tuned,
-        "time_to_gap_s": {"all_judged_instances": t_all, "gap_threshold": 1e-3,
-                          "one_instance_at_a_time": sequential,
-                          "median_gap_per_iter": [float(np.median(g)) for g in gaps],
-                          "max_gap_per_iter": [float(np.max(g)) for g in gaps],
-                          "cstar": f"oracle Method A (FP64) on {len(judged)} seeded instances "
-                                   "(tests/golden/c3_reference_optima.json)",
-                          "judged_instances": [int(b) for b in judged]},
+        "time_to_gap_s": ttg,
     }
 
 
@@ -471,7 +483,7 @@ def bench_single(w, args, steps_req: int, warmup: int):
     # iteration and the one library call that is exactly one kernel, so its
     # HIP-event time on the launch stream is the kernel's duration.
     ro = calls["rollout_kernel"]
-    roofline = {"kernel": "rollout_chain_kernel" if p.model == 2 else "rollout_di_kernel",
+    roofline = {"kernel": "rollout_chain_split_kernel" if p.model == 2 else "rollout_di_kernel",
                 "bound": "hbm", "achieved": ro["GBps"], "peak": PEAK["hbm_GBps"], "unit": "GB/s",
                 "frac": ro["hbm_frac"], "traffic": rollout_traffic(w.name, esize),
                 "algorithmic_bytes": work["rollout"]["bytes"], "launch_us": ro["us"],
@@ -601,6 +613,8 @@ def main():
                     help="seconds of single-thread oracle timing (0: skip)")
     ap.add_argument("--no-extra", action="store_true",
                     help="c2 only: leave out the c4 and c3 objects of the default line")
+    ap.add_argument("--batch-tuning", default="",
+                    help='c3: tuning fields as JSON, e.g. {"rollout_mode": 2} (default: the library\'s)')
     ap.add_argument("--autotune", action="store_true",
                     help="--workload c3: run the launch-shape autotuner before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -295,6 +295,13 @@ typedef struct {
   int32_t contract_blocks_per_cu;  /* persistent grid of S = dR W^T */
   int32_t contract_ksplit;         /* k-slices of S per instance */
   int32_t small_blocks_per_cu;     /* persistent grid of the other steps */
+  int32_t rollout_mode;            /* 1: lane-group rollout storing the
+                                      residuals, then the BF16x3 contraction;
+                                      2: rollout fused with the contraction
+                                      (one lane per sample, pair differences
+                                      contracted on the MFMA, no residuals in
+                                      HBM; the contraction tuning fields do
+                                      not apply); 0: the default (2) */
 } gnmppi_batch_tuning;
 
 size_t gnmppi_batch_workspace(const gnmppi_problem *shared, int32_t count,

@@ -57,7 +57,8 @@ class GnmppiBatchSettings(ctypes.Structure):
 
 class GnmppiBatchTuning(ctypes.Structure):
     _fields_ = [("rollout_blocks_per_cu", c_int32), ("contract_blocks_per_cu", c_int32),
-                ("contract_ksplit", c_int32), ("small_blocks_per_cu", c_int32)]
+                ("contract_ksplit", c_int32), ("small_blocks_per_cu", c_int32),
+                ("rollout_mode", c_int32)]
 
 
 PROBLEM_P = ctypes.POINTER(GnmppiProblem)

@@ -6,11 +6,14 @@ targets, U, status words, line-search info) and the library workspace; one
 ``gnmppi_batch_iteration`` (persistent launches per step and shape class),
 ``capture(iters)`` records iterations into one HIP graph.
 
-``autotune`` is the launch-shape tuner: it times the candidate tunings (grid
-sizes of the persistent launches, k-slices of the sample contraction) on the
+``autotune`` is the launch-shape tuner: it times the candidate tunings on the
 batch itself and keeps the fastest; results are cached per batch shape in a
-JSON file.  Every candidate computes the same iteration (up to the summation
-order of the k-slices).
+JSON file.  The candidates cover the two rollout mappings (a lane group per
+sample storing the residuals, then the BF16x3 contraction; or one lane per
+sample fused with the contraction on the MFMA) and, per mapping, the grid
+sizes of the persistent launches and the k-slices of the separate
+contraction.  Every candidate computes the same iteration up to the
+summation order of the contraction.
 """
 from __future__ import annotations
 
@@ -28,13 +31,28 @@ from . import _lib
 
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "gnmppi", "batch_autotune.json")
 
-# Candidate values of each tuning field (0 = the library's default).
-TUNING_SPACE = {
-    "rollout_blocks_per_cu": (16, 32, 64),
-    "contract_blocks_per_cu": (16, 32, 64),
-    "contract_ksplit": (1, 2),
-    "small_blocks_per_cu": (8, 16, 32),
-}
+# Candidate tunings: a list of spaces, each the product of its value lists
+# (0 = the library's default).  rollout_mode 2 is the fused kernel (the
+# contraction fields do not apply to it), 1 the lane-group rollout followed
+# by the separate contraction.
+TUNING_SPACE = [
+    {"rollout_mode": (2,), "small_blocks_per_cu": (8, 16, 32)},
+    {"rollout_mode": (1,), "rollout_blocks_per_cu": (16, 32, 64),
+     "contract_blocks_per_cu": (16, 32, 64), "contract_ksplit": (1, 2),
+     "small_blocks_per_cu": (8, 16, 32)},
+]
+
+
+def _candidates(space):
+    """The tunings of a space (dict: product of its value lists) or of a list
+    of spaces (their union, in order)."""
+    spaces = [space] if isinstance(space, dict) else list(space)
+    out = []
+    for sp in spaces:
+        names = list(sp)
+        for values in itertools.product(*(sp[k] for k in names)):
+            out.append(dict(zip(names, values)))
+    return out
 
 
 def sigma_schedule(sigma0: float, beta: float, sigma_min: float, it: int) -> float:
@@ -171,10 +189,8 @@ def autotune(batch: BatchGNMPPI, space: dict | None = None, reps: int = 3, cache
             batch.set_tuning(known[key]["tuning"])
             return known[key]
     U0 = batch.U.clone()
-    names = list(space)
     results = []
-    for values in itertools.product(*(space[k] for k in names)):
-        tuning = dict(zip(names, values))
+    for tuning in _candidates(space):
         batch.set_tuning(tuning)
         # timed as graph replays: an eager call also rebuilds the work tables
         # on the host, which a captured iteration never does

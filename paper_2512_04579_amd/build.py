@@ -22,7 +22,7 @@ ARCH = "gfx950"
 # Longest compiles first (the sweep units instantiate one kernel per 16-row
 # class), so the parallel build ends with the short ones.
 SOURCES = ["sweep_batch_inv.hip", "sweep_batch_dir.hip", "sweep_f32.hip", "sweep_f64.hip",
-           "dense.hip", "gemm.hip", "rollout.hip", "abi.cpp", "batch.cpp", "sample.hip", "mppi.hip",
+           "fused.hip", "dense.hip", "gemm.hip", "rollout.hip", "abi.cpp", "batch.cpp", "sample.hip", "mppi.hip",
            "mlp.hip"]
 
 # Packed FP32 VALU ops are switched off for every HIP translation unit.

@@ -29,9 +29,14 @@ constexpr int kCus = 256;  // MI355X compute units: the persistent grids are siz
 
 // Steps of one iteration in launch order; each is split by its shape class.
 enum Step {
-  kSample, kGramW, kReduceG, kSweepG, kRollout, kSplit, kContractS, kReduceS, kJac, kGramH,
-  kReduceH, kSweepH, kLine, kSteps
+  kSample, kGramW, kReduceG, kSweepG, kRollout, kNominal, kFused, kSplit, kContractS, kReduceS,
+  kJac, kGramH, kReduceH, kSweepH, kLine, kSteps
 };
+
+// Rollout modes (gnmppi_batch_tuning.rollout_mode): residuals through HBM
+// (lane-group rollout, then the BF16x3 contraction) or the fused kernel
+// (one lane per sample, contraction on the MFMA, no residuals in HBM).
+constexpr int kModeDefault = 0, kModeUnfused = 1, kModeFused = 2;
 
 struct PlanLaunch {
   Step step;
@@ -61,8 +66,10 @@ bool settings_ok(const gnmppi_batch_settings* s) {
 
 gnmppi_batch_tuning effective(const gnmppi_batch_tuning* t) {
   // defaults: the autotuner's pick for 1024 uneven chain instances
-  gnmppi_batch_tuning d{64, 16, 1, 32};
+  gnmppi_batch_tuning d{64, 16, 1, 32, kModeFused};
   if (t) {
+    if (t->rollout_mode == kModeUnfused || t->rollout_mode == kModeFused)
+      d.rollout_mode = t->rollout_mode;
     if (t->rollout_blocks_per_cu > 0) d.rollout_blocks_per_cu = t->rollout_blocks_per_cu;
     if (t->contract_blocks_per_cu > 0) d.contract_blocks_per_cu = t->contract_blocks_per_cu;
     if (t->contract_ksplit > 0) d.contract_ksplit = t->contract_ksplit;
@@ -94,11 +101,18 @@ Plan make_plan(int count, const gnmppi_batch_instance* in, const gnmppi_batch_se
     d.m = b.N * (4 * b.n_masses + 2);
     d.npad = cdiv(d.n, 16) * 16;
     d.kpad = cdiv(d.K, 32) * 32;
+    const bool fused = tune.rollout_mode == kModeFused;
     const int ksteps = cdiv(d.K, 32);
-    const int ns = std::max(1, std::min(tune.contract_ksplit, ksteps));
-    const int spl = cdiv(ksteps, ns);
-    d.nsplit = cdiv(ksteps, spl);
-    d.split_len = spl * 32;
+    if (fused) {
+      // one partial sum of S per block of kFusedPairs antithetic pairs
+      d.nsplit = cdiv(d.K / 2, kFusedPairs);
+      d.split_len = 2 * kFusedPairs;
+    } else {
+      const int ns = std::max(1, std::min(tune.contract_ksplit, ksteps));
+      const int spl = cdiv(ksteps, ns);
+      d.nsplit = cdiv(ksteps, spl);
+      d.split_len = spl * 32;
+    }
     d.gsplit = 1;
     d.gsplit_len = ksteps * 32;
     d.hsplit = std::max(1, std::min(16, cdiv(d.m, 128)));
@@ -111,11 +125,13 @@ Plan make_plan(int count, const gnmppi_batch_instance* in, const gnmppi_batch_se
     tiles[kGramW][i] = batch_contract_row_blocks(d.n, 0) * d.gsplit;
     tiles[kReduceG][i] = d.n;
     tiles[kSweepG][i] = 1;
-    tiles[kRollout][i] = batch_rollout_tiles(d.M, d.K);
+    tiles[kRollout][i] = fused ? 0 : batch_rollout_tiles(d.M, d.K);
+    tiles[kNominal][i] = fused ? 1 : 0;
+    tiles[kFused][i] = fused ? d.nsplit : 0;
     tiles[kSplit][i] = 0;  // the sampler writes the bf16 planes itself
-    tiles[kContractS][i] = batch_bf16_row_blocks(d.m) * d.nsplit;
+    tiles[kContractS][i] = fused ? 0 : batch_bf16_row_blocks(d.m) * d.nsplit;
     // one k-slice: the partial sum already is S (no reduction)
-    tiles[kReduceS][i] = d.nsplit > 1 ? cdiv(d.m, 4) * cdiv(d.n, 64) : 0;
+    tiles[kReduceS][i] = d.nsplit > 1 ? cdiv(d.m, 16) * cdiv(d.npad, 64) : 0;
     tiles[kJac][i] = batch_contract_row_blocks(d.m, 1);
     tiles[kGramH][i] = d.hsplit;
     tiles[kReduceH][i] = d.n + 1;
@@ -136,7 +152,8 @@ Plan make_plan(int count, const gnmppi_batch_instance* in, const gnmppi_batch_se
       case kGramW: case kContractS: case kJac: return cdiv(d.n, 16);
       case kSweepG: return cdiv(d.n, 16);
       case kGramH: case kSweepH: return cdiv(d.n + 1, 16);
-      case kRollout: case kLine: return batch_chain_group(d.M);
+      case kRollout: case kNominal: case kLine: return batch_chain_group(d.M);
+      case kFused: return 0;  // one launch for every chain length
       default: return 0;
     }
   };
@@ -144,7 +161,8 @@ Plan make_plan(int count, const gnmppi_batch_instance* in, const gnmppi_batch_se
     switch (s) {
       case kRollout: return tune.rollout_blocks_per_cu * kCus;
       case kContractS: return tune.contract_blocks_per_cu * kCus;
-      case kSweepG: case kSweepH: case kLine: return 8 * kCus;
+      case kSweepG: case kSweepH: case kLine: case kNominal: return 8 * kCus;
+      case kFused: return kCus;  // one 512-thread block per CU (157 KB of LDS)
       default: return tune.small_blocks_per_cu * kCus;
     }
   };
@@ -182,7 +200,10 @@ Plan make_plan(int count, const gnmppi_batch_instance* in, const gnmppi_batch_se
     d.status = b.status;
     d.info = b.info;
     d.W = reinterpret_cast<float*>(take(sizeof(float) * d.n * d.ldw));
-    d.R = reinterpret_cast<float*>(take(sizeof(float) * static_cast<size_t>(d.m) * d.ldr));
+    // the fused path keeps the residuals on chip
+    d.R = tune.rollout_mode == kModeFused
+              ? nullptr
+              : reinterpret_cast<float*>(take(sizeof(float) * static_cast<size_t>(d.m) * d.ldr));
     d.C = nullptr;  // the GN-MPPI step never reads the perturbed columns' costs
     d.r0 = reinterpret_cast<float*>(take(sizeof(float) * d.m));
     d.c0 = reinterpret_cast<float*>(take(sizeof(float)));
@@ -231,6 +252,8 @@ hipError_t run_iteration(const Plan& pl, const gnmppi_problem& shared, char* bas
       case kReduceG: e = launch_batch_reduce_sym(0, inst, bl, 0.0, st); break;
       case kSweepG: e = launch_batch_sweep(0, L.cls, inst, bl, st); break;
       case kRollout: e = launch_batch_rollout(L.cls, inst, bl, shared, pl.N_max, st); break;
+      case kNominal: e = launch_batch_nominal(L.cls, inst, bl, shared, pl.N_max, st); break;
+      case kFused: e = launch_batch_fused(inst, bl, shared, st); break;
       case kSplit: e = launch_batch_split_bf16(inst, bl, st); break;
       case kContractS: e = launch_batch_contract_bf16(L.cls, inst, bl, st); break;
       case kReduceS: e = launch_batch_reduce_rows(inst, bl, st); break;

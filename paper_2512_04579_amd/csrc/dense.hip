@@ -138,15 +138,41 @@ __global__ void __launch_bounds__(256) reduce_rows_kernel(const T* __restrict__ 
                        blockIdx.y);
 }
 
-// Batched S = sum of the k-slices; tile = row group * ceil(n / 64) + column group.
+// Batched S = sum of the k-slices over all npad columns (the padding columns
+// of every slice are zero): tile = row group * ceil(npad / 64) + column
+// group, 16 rows x 64 columns per block, four columns per thread with 16-byte
+// loads, eight slices in flight, summed in slice order in double precision.
 __global__ void __launch_bounds__(256) batch_reduce_rows_kernel(const BatchInst* __restrict__ inst,
                                                                 BatchLaunch L) {
+  using f32x4 = float __attribute__((ext_vector_type(4)));
   for (int w = blockIdx.x; w < L.count; w += gridDim.x) {
     const BatchItem it = L.items[w];
     const BatchInst& b = inst[it.inst];
-    const int xb = (b.n + 63) / 64;
-    reduce_rows_block<float>(b.part, b.nsplit, static_cast<int64_t>(b.m) * b.npad, b.npad, b.m,
-                             b.n, 1.0, b.S, b.npad, nullptr, it.tile % xb, it.tile / xb);
+    const int xb = (b.npad + 63) / 64;
+    const int i = (it.tile / xb) * 16 + (threadIdx.x >> 4);
+    const int c = (it.tile % xb) * 64 + 4 * (threadIdx.x & 15);
+    if (i >= b.m || c >= b.npad) continue;
+    const int64_t stride = static_cast<int64_t>(b.m) * b.npad;
+    const float* src = b.part + static_cast<int64_t>(i) * b.npad + c;
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    constexpr int U = 8;
+    for (int sp = 0; sp < b.nsplit; sp += U) {
+      f32x4 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        v[u] = sp + u < b.nsplit ? *reinterpret_cast<const f32x4*>(src + (sp + u) * stride)
+                                 : f32x4{0, 0, 0, 0};
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        a0 += static_cast<double>(v[u][0]);
+        a1 += static_cast<double>(v[u][1]);
+        a2 += static_cast<double>(v[u][2]);
+        a3 += static_cast<double>(v[u][3]);
+      }
+    }
+    *reinterpret_cast<f32x4*>(b.S + static_cast<int64_t>(i) * b.npad + c) =
+        f32x4{static_cast<float>(a0), static_cast<float>(a1), static_cast<float>(a2),
+              static_cast<float>(a3)};
   }
 }
 

@@ -137,6 +137,14 @@ int batch_rollout_tiles(int M, int K);
 size_t batch_rollout_lds(int G, int N);
 hipError_t launch_batch_rollout(int G, const BatchInst* inst, const BatchLaunch& L,
                                 const gnmppi_problem& shared, int N_max, hipStream_t st);
+hipError_t launch_batch_nominal(int G, const BatchInst* inst, const BatchLaunch& L,
+                                const gnmppi_problem& shared, int N_max, hipStream_t st);
+// Fused rollout + sample contraction (fused.hip): one launch for every mass
+// count; item = (instance, block of 128 antithetic pairs); writes the item's
+// partial sum of S.
+constexpr int kFusedPairs = 128;
+hipError_t launch_batch_fused(const BatchInst* inst, const BatchLaunch& L,
+                              const gnmppi_problem& shared, hipStream_t st);
 hipError_t launch_batch_line_search(int G, const BatchInst* inst, const BatchLaunch& L,
                                     const gnmppi_problem& shared, int n_alpha, int N_max,
                                     hipStream_t st);

@@ -526,6 +526,24 @@ __global__ void __launch_bounds__(256) batch_rollout_kernel(const BatchInst* __r
   }
 }
 
+// Batched nominal rollout alone (the fused rollout-contraction path needs no
+// nominal column): item = instance, the nominal U rolled out by one lane
+// group; r0 and c0 as in the rollout above.
+template <int G>
+__global__ void __launch_bounds__(256) batch_nominal_kernel(const BatchInst* __restrict__ inst,
+                                                            BatchLaunch L, ChainDev<float> cd0) {
+  extern __shared__ unsigned char ctl_raw[];
+  for (int w = blockIdx.x; w < L.count; w += gridDim.x) {
+    const BatchInst& b = inst[L.items[w].inst];
+    ChainDev<float> cd = cd0;
+    cd.M = b.M;
+    rollout_chain_block<float, G, kBatchFlushSteps>(cd, b.N, b.x0, b.q, b.r, b.xref, b.U, nullptr,
+                                                    b.ldw, 0, nullptr, b.ldr, nullptr, b.r0, b.c0,
+                                                    1, 1, 0, ctl_raw);
+    __syncthreads();  // the next item reuses the LDS
+  }
+}
+
 // ---- double integrator -----------------------------------------------------
 
 template <typename T, int D, bool STORE, class Ctrl>
@@ -871,6 +889,30 @@ hipError_t launch_batch_rollout(int G, const BatchInst* inst, const BatchLaunch&
       break;
     case 16:
       hipLaunchKernelGGL(batch_rollout_kernel<16>, dim3(L.blocks), dim3(kBlock), lds, st, inst, L, cd);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_nominal(int G, const BatchInst* inst, const BatchLaunch& L,
+                                const gnmppi_problem& shared, int N_max, hipStream_t st) {
+  if (L.count == 0) return hipSuccess;
+  const ChainDev<float> cd = chain_dev<float>(shared);
+  const size_t lds = batch_rollout_lds(G, N_max);
+  switch (G) {
+    case 4:
+      hipLaunchKernelGGL(batch_nominal_kernel<4>, dim3(L.blocks), dim3(kBlock), lds, st, inst, L,
+                         cd);
+      break;
+    case 8:
+      hipLaunchKernelGGL(batch_nominal_kernel<8>, dim3(L.blocks), dim3(kBlock), lds, st, inst, L,
+                         cd);
+      break;
+    case 16:
+      hipLaunchKernelGGL(batch_nominal_kernel<16>, dim3(L.blocks), dim3(kBlock), lds, st, inst, L,
+                         cd);
       break;
     default:
       return hipErrorInvalidValue;

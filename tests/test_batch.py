@@ -17,7 +17,7 @@ import pytest
 import torch
 
 import workloads as wl
-from _parity import TOL, assert_parity, rnd, round_problem
+from _parity import TOL, assert_parity, rel_err, rnd, round_problem
 from oracle import ggn, jacobian, ocp, philox, solvers
 from paper_2512_04579_amd import _lib
 from paper_2512_04579_amd.batch import BatchGNMPPI, autotune
@@ -40,11 +40,17 @@ def _settings():
                              n_alpha=16, contraction="bf16x3")
 
 
+# rollout_mode 1: lane-group rollout storing the residuals, then the BF16x3
+# contraction; 2: one lane per sample fused with the contraction
+MODES = [1, 2]
+
+
 @pytest.mark.gpu
-def test_batch_first_iteration_matches_oracle():
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_first_iteration_matches_oracle(mode):
     inst = _instances()
     st = _settings()
-    batch = BatchGNMPPI(inst, st, seed=11)
+    batch = BatchGNMPPI(inst, st, seed=11, tuning={"rollout_mode": mode})
     batch.step(0)
     torch.cuda.synchronize()
     status = batch.status.cpu().numpy()
@@ -69,7 +75,8 @@ C3_SHAPES = [(4, 20, 512), (5, 28, 1024), (9, 36, 2048), (16, 44, 4096), (4, 52,
 
 
 @pytest.mark.gpu
-def test_batch_every_c3_shape_class_matches_oracle():
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_every_c3_shape_class_matches_oracle(mode):
     inst = []
     for i, (M, N, K) in enumerate(C3_SHAPES):
         prob, x0 = wl.chain_problem(n_masses=M, N=N, dt=0.05, seed=70 + i)
@@ -77,7 +84,7 @@ def test_batch_every_c3_shape_class_matches_oracle():
     classes = {(-(-p.n // 16), -(-(p.n + 1) // 16)) for p, _, _ in inst}
     assert {c for c, _ in classes} == set(range(3, 11)) and {h for _, h in classes} == set(range(3, 12))
     st = _settings()
-    batch = BatchGNMPPI(inst, st, seed=31)
+    batch = BatchGNMPPI(inst, st, seed=31, tuning={"rollout_mode": mode})
     batch.step(0)
     torch.cuda.synchronize()
     status, info = batch.status.cpu().numpy(), batch.info.cpu().numpy()
@@ -100,6 +107,34 @@ def test_batch_every_c3_shape_class_matches_oracle():
 
 
 @pytest.mark.gpu
+def test_fused_rollout_contraction_matches_the_unfused_path():
+    # the same iteration through both mappings: S from the pair differences
+    # contracted on chip against S from the stored residuals.  Both sum BF16x3
+    # products (hi hi + hi lo + lo hi of bf16 splits, about 2^-17 relative per
+    # product) of differently rounded operands in a different order, so each
+    # is within the float32 bar of the oracle and they agree to that bar
+    inst = _instances()
+    for i, (M, N, K) in enumerate(C3_SHAPES[-3:]):
+        prob, x0 = wl.chain_problem(n_masses=M, N=N, dt=0.05, seed=90 + i)
+        inst.append((prob, x0, K))
+    st = _settings()
+    out = {}
+    for mode in MODES:
+        batch = BatchGNMPPI(inst, st, seed=13, tuning={"rollout_mode": mode})
+        batch.step(0)
+        torch.cuda.synchronize()
+        assert (batch.status.cpu().numpy() == 0).all()
+        out[mode] = (batch.U.cpu().numpy().astype(np.float64), batch.info.cpu().numpy())
+    for b in range(len(inst)):
+        sl = slice(int(batch.n_off[b]), int(batch.n_off[b + 1]))
+        assert out[2][1][b, 0] == out[1][1][b, 0], (b, out[2][1][b], out[1][1][b])
+        e = assert_parity(out[2][0][sl], out[1][0][sl], "f32", f"instance {b} U")
+        print(f"instance {b} {batch.problems[b].n_masses, batch.problems[b].N, int(batch.K[b])}: "
+              f"U fused vs unfused {e:.2e}")
+        assert_parity([out[2][1][b, 1]], [out[1][1][b, 1]], "f32", f"instance {b} cost")
+
+
+@pytest.mark.gpu
 def test_batch_matches_the_single_instance_solver():
     inst = _instances()
     st = _settings()
@@ -113,11 +148,22 @@ def test_batch_matches_the_single_instance_solver():
         single = GNMPPI(DeviceProblem(p, "f32"), x0, s1, seed=21 + b, max_iters=2)
         single.solve(2)
         torch.cuda.synchronize()
-        costs, _, status = single.history(2)
+        costs, alphas, status = single.history(2)
         assert (status == 0).all()
         assert_parity([batch.info[b, 1].item()], [costs[1]], "f32", f"instance {b} cost")
-        assert_parity(batch.controls(b).double().cpu().numpy(), single.U.double().cpu().numpy(), "f32",
-                      f"instance {b} U")
+        # the second step is small near the optimum; when the two solvers'
+        # candidate costs are within rounding of each other they may pick
+        # different step lengths, both valid, and then U differs by that
+        # fraction of the step: U is compared when the step lengths agree
+        print(f"instance {b}: alpha batch {batch.info[b, 0].item()} single {alphas[1]}; U rel diff "
+              f"{rel_err(batch.controls(b).double().cpu().numpy(), single.U.double().cpu().numpy()):.2e}")
+        if batch.info[b, 0].item() == alphas[1]:
+            assert_parity(batch.controls(b).double().cpu().numpy(), single.U.double().cpu().numpy(),
+                          "f32", f"instance {b} U")
+        else:
+            C_single = single.C_line.double().cpu().numpy()
+            j = int(batch.info[b, 2].item())
+            assert C_single[j] <= C_single.min() * (1 + 10 * TOL["f32"]), (b, j, C_single)
 
 
 @pytest.mark.gpu
@@ -149,16 +195,20 @@ def test_batch_tunings_compute_the_same_iteration(tmp_path):
     ref.step(0)
     torch.cuda.synchronize()
     U_ref = ref.U.cpu().numpy()
-    for tuning in ({"contract_ksplit": 1, "rollout_blocks_per_cu": 1},
-                   {"contract_ksplit": 4, "contract_blocks_per_cu": 4, "small_blocks_per_cu": 1}):
+    for tuning in ({"contract_ksplit": 1, "rollout_blocks_per_cu": 1, "rollout_mode": 1},
+                   {"contract_ksplit": 4, "contract_blocks_per_cu": 4, "small_blocks_per_cu": 1,
+                    "rollout_mode": 1},
+                   {"rollout_mode": 2, "small_blocks_per_cu": 1}):
         b = BatchGNMPPI(inst, st, seed=8, tuning=tuning)
         b.step(0)
         torch.cuda.synchronize()
         assert_parity(b.U.cpu().numpy(), U_ref, "f32", str(tuning))
     b = BatchGNMPPI(inst, st, seed=8)
-    entry = autotune(b, space={"contract_ksplit": (1, 2), "rollout_blocks_per_cu": (1, 2)}, reps=1,
+    entry = autotune(b, space=[{"rollout_mode": (2,)},
+                               {"rollout_mode": (1,), "contract_ksplit": (1, 2),
+                                "rollout_blocks_per_cu": (1, 2)}], reps=1,
                      cache=str(tmp_path / "tune.json"))
-    assert entry["candidates"] == 4 and entry["tuning"] == b.tuning
+    assert entry["candidates"] == 5 and entry["tuning"] == b.tuning
     b.step(0)
     torch.cuda.synchronize()
     assert_parity(b.U.cpu().numpy(), U_ref, "f32", "autotuned")

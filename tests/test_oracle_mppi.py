@@ -79,3 +79,56 @@ def test_nonfinite_costs_get_zero_weight():
     np.testing.assert_allclose(mppi.step(W, C, 1.0), [3.0])
     with pytest.raises(mppi.NoFiniteCost):
         mppi.weights(np.array([np.nan, np.inf]), 1.0)
+
+
+def _di_cost_closed_form(x0, U, N, dt, q, r):
+    """Cost of the double-integrator pair (Problem IV's model, two axes)
+    from the stacked closed form x_{k+1} = A^{k+1} x0 + sum_{j<=k} A^{k-j} B
+    u_j, written out here with A = [[I, dt I], [0, I]], B = [[dt^2/2 I], [dt I]]
+    and the stage cost q |x_{k+1}|^2 + r |u_k|^2 (x_ref = 0)."""
+    I2 = np.eye(2)
+    A = np.block([[I2, dt * I2], [np.zeros((2, 2)), I2]])
+    B = np.vstack([0.5 * dt * dt * I2, dt * I2])
+    u = np.asarray(U).reshape(N, 2)
+    total = 0.0
+    for k in range(N):
+        x = np.linalg.matrix_power(A, k + 1) @ x0
+        for j in range(k + 1):
+            x = x + np.linalg.matrix_power(A, k - j) @ B @ u[j]
+        total += q * x @ x + r * u[k] @ u[k]
+    return total
+
+
+def test_plain_mppi_laplace_limit_is_greedy_random_search():
+    # With a vanishing temperature the weights of Eq. (8) collapse onto the
+    # cheapest sample (the Laplace limit of Sec. 3), so Method C becomes
+    # greedy random search: U <- U + W[:, argmin_s C(U + W_s)].  The greedy
+    # search below evaluates its costs by the closed form above, a route
+    # independent of the oracle's simulator; six iterations must agree.
+    import workloads as wl
+    from oracle import solvers
+    N, dt = 6, 0.1
+    prob = wl.double_integrator_problem(axes=2, dt=dt, N=N)
+    x0 = np.array([0.7, -0.4, 0.2, 0.5])
+    noise = lambda it, s: wl.gaussian_perturbations(prob.n, 16, s, 300 + it)  # noqa: E731
+    U_or, _ = solvers.plain_mppi(prob, x0, np.zeros(prob.n), 6, noise, 0.3, temperature=1e-12,
+                                 beta=0.9)
+    U = np.zeros(prob.n)
+    for it in range(6):
+        W = noise(it, 0.3 * 0.9 ** (0.5 * it))
+        costs = [_di_cost_closed_form(x0, U + W[:, s], N, dt, 1.0, 0.1) for s in range(W.shape[1])]
+        U = U + W[:, int(np.argmin(costs))]
+    np.testing.assert_allclose(U_or, U, rtol=0, atol=1e-14)
+
+
+def test_plain_mppi_uniform_limit_keeps_u_with_antithetic_samples():
+    # An infinite temperature gives equal weights, so the update of Eq. (7) is
+    # the plain mean of W, exactly zero for antithetic pairs: U stays put.
+    import workloads as wl
+    from oracle import solvers
+    prob = wl.double_integrator_problem(axes=2, dt=0.1, N=5)
+    U0 = np.random.default_rng(4).standard_normal(prob.n)
+    noise = lambda it, s: wl.gaussian_perturbations(prob.n, 32, s, 400 + it)  # noqa: E731
+    U, _ = solvers.plain_mppi(prob, np.array([0.1, 0.2, 0.3, 0.4]), U0, 3, noise, 0.5,
+                              temperature=1e300)
+    np.testing.assert_allclose(U, U0, rtol=0, atol=1e-15)
