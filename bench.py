@@ -59,6 +59,11 @@ def algorithmic_work(prob, K: int, L: int, esize: int):
         "jacobian": {"bytes": m * K * esize + n * K * esize + m * n * esize,
                      "flops": 2.0 * m * n * K + 2.0 * n * n * K + 2.0 * m * n * n},
         "ggn_step": {"bytes": m * n * esize + m * esize, "flops": 2.0 * m * (n + 1) ** 2 + n ** 3 / 3.0},
+        # the direction without J: S and G from one contraction, the normal
+        # matrix of [S r0], the solve and dU = G y
+        "direction": {"bytes": m * K * esize + n * K * esize + m * esize,
+                      "flops": 2.0 * (m + n) * n * K + 2.0 * m * (n + 1) ** 2 + n ** 3 / 3.0
+                      + 2.0 * n * n},
         "sample": {"bytes": n * K * esize, "flops": 0.0},
         "line_search": {"bytes": 0, "flops": L * N * fss},
     }
@@ -156,17 +161,19 @@ def reference_c3(inst):
     return rows
 
 
-def pick_overlap(dp, x0, st, seed: int, iters: int = 50) -> str:
-    """The fastest side-stream schedule ("ahead", "prefetch" or "same", see GNMPPI) for
-    this problem: a graph of ``iters`` captured iterations per schedule (the
-    length of the timed graphs: "ahead" pays for its first iteration's side
-    work once per graph), three replays each, the shortest replay counts."""
+def pick_schedule(dp, x0, st, seed: int, iters: int = 50) -> str:
+    """The fastest iteration schedule (SCHEDULES in the solver module: the
+    direction without J on one stream, or J formed with G^{-1} on a side
+    stream in one of three orders) for this problem: a graph of ``iters``
+    captured iterations per schedule (the length of the timed graphs: "ahead"
+    pays for its first iteration's side work once per graph), three replays
+    each, the shortest replay counts."""
     import torch
 
-    from paper_2512_04579_amd.solver import GNMPPI
-    best, pick = None, "ahead"
-    for mode in ("ahead", "prefetch", "same"):
-        solver = GNMPPI(dp, x0, st, seed=seed, max_iters=iters, overlap=mode)
+    from paper_2512_04579_amd.solver import make_solver
+    best, pick = None, "direct"
+    for mode in ("direct", "ahead", "prefetch", "same"):
+        solver = make_solver(dp, x0, st, mode, seed=seed, max_iters=iters)
         graph = solver.capture(iters)
         graph.replay()
         torch.cuda.synchronize()
@@ -192,7 +199,7 @@ def bench_sweep(args):
 
     import workloads as wl
     from paper_2512_04579_amd.problem import DeviceProblem
-    from paper_2512_04579_amd.solver import GNMPPI
+    from paper_2512_04579_amd.solver import make_solver
 
     base = wl.c2()
     rows = []
@@ -201,8 +208,8 @@ def bench_sweep(args):
         dp = DeviceProblem(prob, "f32")
         for K in (512, 1024, 2048, 4096, 8192):
             st = dataclasses.replace(base.settings, K=K)
-            mode = pick_overlap(dp, x0, st, seed=1)
-            solver = GNMPPI(dp, x0, st, seed=1, max_iters=51, overlap=mode)
+            mode = pick_schedule(dp, x0, st, seed=1)
+            solver = make_solver(dp, x0, st, mode, seed=1, max_iters=51)
             graph = solver.capture(50)
             graph.replay()
             torch.cuda.synchronize()
@@ -213,7 +220,7 @@ def bench_sweep(args):
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / 50
             progress(f"sweep N={N} K={K}: {1e3 * ms:.1f} us/iteration")
-            rows.append({"N": N, "K": K, "m": prob.m, "n": prob.n, "overlap": mode,
+            rows.append({"N": N, "K": K, "m": prob.m, "n": prob.n, "schedule": mode,
                          "us_per_iter": 1e3 * ms,
                          "iters_per_s": 1e3 / ms,
                          "sample_steps_per_s": (K + 1 + st.n_alpha) * N / (ms * 1e-3)})
@@ -399,7 +406,7 @@ def bench_single(w, args, steps_req: int, warmup: int):
 
     from paper_2512_04579_amd import _lib
     from paper_2512_04579_amd.problem import DeviceProblem
-    from paper_2512_04579_amd.solver import GNMPPI, PlainMPPI
+    from paper_2512_04579_amd.solver import GNMPPI, PlainMPPI, make_solver
 
     p, st = w.problem, w.settings
     dp = DeviceProblem(p, w.dtype)
@@ -409,17 +416,17 @@ def bench_single(w, args, steps_req: int, warmup: int):
     chunk = min(steps_req, args.graph_chunk)
     reps = max(1, steps_req // chunk)
     steps = reps * chunk
-    # In a graph the factorisation of G = W W^T (which needs only W) runs on a
-    # side stream, in the fastest of the three schedules; eager launches keep
-    # one stream.
+    # The graphs run the fastest of the iteration schedules (the direction
+    # without J on one stream, or J formed with G^{-1} on a side stream);
+    # eager launches run the direction without J.
     if args.eager:
-        overlap = False
-    elif args.overlap == "auto":
-        overlap = pick_overlap(dp, w.x0, st, seed=w.noise_seed, iters=chunk)
+        schedule = "direct"
+    elif args.schedule == "auto":
+        schedule = pick_schedule(dp, w.x0, st, seed=w.noise_seed, iters=chunk)
     else:
-        overlap = args.overlap
-    progress(f"side-stream schedule: {overlap}")
-    solver = GNMPPI(dp, w.x0, st, seed=w.noise_seed, max_iters=chunk + 1, overlap=overlap)
+        schedule = args.schedule
+    progress(f"iteration schedule: {schedule}")
+    solver = make_solver(dp, w.x0, st, schedule, seed=w.noise_seed, max_iters=chunk + 1)
     graph = solver.capture(chunk) if not args.eager else None
     for _ in range(max(1, warmup // chunk)):
         graph.replay() if graph else [solver.step(it) for it in range(chunk)]
@@ -504,14 +511,14 @@ def bench_single(w, args, steps_req: int, warmup: int):
         "data": "synthetic",
         "config": {"workload": w.description, "name": w.name, "nx": p.nx, "nu": p.nu, "N": N, "K": K,
                    "m": p.m, "n": p.n, "line_search_candidates": L, "jacobian": st.jacobian,
-                   "contraction": st.contraction, "overlap": overlap},
+                   "contraction": st.contraction, "schedule": schedule},
         "sample_steps_per_s": steps * (K + 1 + L) * N / (ms_total * 1e-3),
         "host_wall_s": wall,
         "per_call": calls,
         "iteration_over_rollout": ms_per_step * 1e3 / per_call_us["rollout_kernel"],
         "timed_with": "eager launches" if args.eager else
-        f"HIP graph replays of {chunk} iterations, G = W W^T factored on a side stream "
-        f"(schedule {overlap!r}" + (", the fastest of three timed at start-up)" if args.overlap == "auto" else ")"),
+        f"HIP graph replays of {chunk} iterations, schedule {schedule!r}"
+        + (" (the fastest of four timed at start-up)" if args.schedule == "auto" else ""),
         "roofline": roofline,
     }
 
@@ -622,15 +629,19 @@ def main():
     ap.add_argument("--mppi-iters", type=int, default=1500)
     ap.add_argument("--graph-chunk", type=int, default=50, help="iterations per captured graph")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graphs")
-    ap.add_argument("--overlap", choices=("auto", "ahead", "prefetch", "same"), default="auto",
-                    help="side-stream schedule of the graphs (auto: the fastest of the three)")
+    ap.add_argument("--schedule", choices=("auto", "direct", "formed", "ahead", "prefetch", "same"),
+                    default="auto",
+                    help="iteration schedule of the graphs: direct = the GGN direction without "
+                         "forming J, one stream; formed = J formed, one stream; ahead / prefetch "
+                         "/ same = J formed, G^{-1} on a side stream (auto: the fastest of "
+                         "direct, ahead, prefetch, same)")
     ap.add_argument("--kernel-reps", type=int, default=50, help="rollout launches for the roofline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "design is described but not built", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
+              "described but not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

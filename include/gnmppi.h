@@ -215,6 +215,42 @@ int gnmppi_ggn_step(int32_t dtype, int32_t m, int32_t n, const void *J,
                     double lm_lambda, void *dU, void *work, size_t work_bytes,
                     int32_t *status, void *stream);
 
+/* ---- a4 + a5 without forming J (Eqs. (10), (13)) ------------------------
+ * The GGN direction of gnmppi_ggn_step for the Jacobian that
+ * gnmppi_reconstruct_jacobian(..., method, ...) would form, computed from
+ * S = (R - r0 1^T) W^T directly.  With J = S A (LS: A = G^{-1}, G = W W^T;
+ * MC: A = I / (K sigma2)) and B = A^{-1}, J^T J + lm_lambda I equals
+ * A (S^T S + lm_lambda B^2) A and J^T r0 = A S^T r0, so
+ *   dU = B y  with  (S^T S + lm_lambda B^2) y = -S^T r0,
+ * the same minimiser of the GGN subproblem up to rounding.  LS solves this
+ * system (the normal matrix of [S r0], plus lm_lambda G^2, accumulated in
+ * double precision; the sweep of gnmppi_ggn_step; then dU = G y), so the
+ * m x n x n product J = S G^{-1} is never formed; G comes out of the same
+ * contraction as S (the rows of W appended to those of R - r0 1^T), or,
+ * with GNMPPI_JAC_GRAM_READY, from gnmppi_perturbation_gram on the same
+ * `work` (which then also reports the rank check of G).  MC forms
+ * J = S / (K sigma2) and takes the plain GGN step.
+ * Arguments as in gnmppi_reconstruct_jacobian and gnmppi_ggn_step (r0
+ * contiguous).  method: GNMPPI_JAC_LS (optionally | GNMPPI_JAC_GRAM_READY)
+ * or GNMPPI_JAC_MC, either with GNMPPI_JAC_BF16 or GNMPPI_JAC_BF16X3 (F32).
+ * LS also takes GNMPPI_JAC_S_ONLY (only the k-slice partials of the
+ * contraction; status not written) and GNMPPI_JAC_APPLY_ONLY (the rest, from
+ * those partials, with the same other method bits; R and W not read), so that
+ * only the second half needs to wait for gnmppi_perturbation_gram.  A pivot
+ * at or below n 2^-52 times the largest diagonal entry of the system sets
+ * *status = GNMPPI_ENOTPD and dU = 0 (a rank-deficient W makes S^T S
+ * singular).  1 <= n <= 192.  `work`: at least
+ * gnmppi_ggn_direction_workspace(...) bytes, 256-byte aligned: the Jacobian
+ * workspace (its G region is what gnmppi_perturbation_gram writes) followed
+ * by the GGN workspace. */
+size_t gnmppi_ggn_direction_workspace(int32_t dtype, int32_t m, int32_t n, int32_t K);
+int gnmppi_ggn_direction(int32_t dtype, int32_t m, int32_t n, int32_t K,
+                         const void *R, int64_t ldr, const void *r0,
+                         const void *W, int64_t ldw, int32_t method,
+                         double sigma2, double lm_lambda, void *dU,
+                         void *work, size_t work_bytes, int32_t *status,
+                         void *stream);
+
 /* For callers that cannot allocate device memory -- code under HIP graph
  * capture that may not call hipMalloc, tight serving loops, harnesses that
  * forbid allocation: gnmppi_ggn_step with no `work` argument.  Its scratch

@@ -86,6 +86,10 @@ SIGNATURES = {
     "gnmppi_ggn_workspace": (c_size_t, [c_int32, c_int32, c_int32]),
     "gnmppi_ggn_step": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_int64, c_void_p, c_int64,
                                   c_double, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
+    "gnmppi_ggn_direction_workspace": (c_size_t, [c_int32, c_int32, c_int32, c_int32]),
+    "gnmppi_ggn_direction": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p, c_int64,
+                                       c_void_p, c_void_p, c_int64, c_int32, c_double, c_double,
+                                       c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
     "gnmppi_ggn_step_noalloc": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_int64, c_void_p,
                                           c_int64, c_double, c_void_p, c_void_p, c_void_p]),
     "gnmppi_line_search": (c_int32, [PROBLEM_P, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
@@ -238,6 +242,22 @@ def gnmppi_ggn_step(J, r0, lm_lambda: float, dU, work, status=None, inc_r0: int 
     _check("gnmppi_ggn_step", load().gnmppi_ggn_step(
         _dtype_code(J), m, n, _ptr(J), _ld(J), _ptr(r0), int(inc_r0), float(lm_lambda), _ptr(dU),
         _ptr(work), work.numel() * work.element_size(), _ptr(status), _stream(stream)))
+
+
+def gnmppi_ggn_direction_workspace(dtype: int, m: int, n: int, K: int) -> int:
+    return int(load().gnmppi_ggn_direction_workspace(dtype, m, n, K))
+
+
+def gnmppi_ggn_direction(R, r0, W, dU, work, method: int, sigma2: float = 0.0,
+                         lm_lambda: float = 0.0, status=None, m: int | None = None,
+                         K: int | None = None, stream=None):
+    m = r0.numel() if m is None else m
+    n = dU.numel()
+    K = W.shape[1] if K is None else K
+    _check("gnmppi_ggn_direction", load().gnmppi_ggn_direction(
+        _dtype_code(dU), int(m), n, K, _ptr(R), _ld(R), _ptr(r0), _ptr(W), _ld(W), int(method),
+        float(sigma2), float(lm_lambda), _ptr(dU), _ptr(work), work.numel() * work.element_size(),
+        _ptr(status), _stream(stream)))
 
 
 def gnmppi_ggn_step_noalloc(J, r0, lm_lambda: float, dU, status=None, inc_r0: int = 1,

@@ -149,6 +149,42 @@ int gnmppi_ggn_step(int32_t dtype, int32_t m, int32_t n, const void* J, int64_t 
                                    as_stream(stream)));
 }
 
+size_t gnmppi_ggn_direction_workspace(int32_t dtype, int32_t m, int32_t n, int32_t K) {
+  if (!dtype_ok(dtype) || m < 1 || n < 1 || K < 1) return 0;
+  return gnm::ggn_direction_bytes(dtype, m, n, K);
+}
+
+int gnmppi_ggn_direction(int32_t dtype, int32_t m, int32_t n, int32_t K, const void* R,
+                         int64_t ldr, const void* r0, const void* W, int64_t ldw, int32_t method,
+                         double sigma2, double lm_lambda, void* dU, void* work, size_t work_bytes,
+                         int32_t* status, void* stream) {
+  if (!dtype_ok(dtype) || m < 1 || n < 1 || n > 192 || K < 1) return GNMPPI_EINVAL;
+  if (R == nullptr || r0 == nullptr || W == nullptr || dU == nullptr || work == nullptr)
+    return GNMPPI_EINVAL;
+  if (ldr < K || ldw < K) return GNMPPI_EINVAL;
+  const int32_t base = method & 0xff, flags = method & ~0xff;
+  if (flags & ~(GNMPPI_JAC_GRAM_READY | GNMPPI_JAC_BF16 | GNMPPI_JAC_BF16X3 | GNMPPI_JAC_S_ONLY |
+                GNMPPI_JAC_APPLY_ONLY))
+    return GNMPPI_EINVAL;
+  // MC has no G (and nothing to split around it)
+  if (base == GNMPPI_JAC_MC) {
+    if (flags & (GNMPPI_JAC_GRAM_READY | GNMPPI_JAC_S_ONLY | GNMPPI_JAC_APPLY_ONLY))
+      return GNMPPI_EINVAL;
+    if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return GNMPPI_EINVAL;
+  } else if (base != GNMPPI_JAC_LS) {
+    return GNMPPI_EINVAL;
+  }
+  if ((flags & GNMPPI_JAC_S_ONLY) && (flags & GNMPPI_JAC_APPLY_ONLY)) return GNMPPI_EINVAL;
+  if ((flags & GNMPPI_JAC_BF16) && (flags & GNMPPI_JAC_BF16X3)) return GNMPPI_EINVAL;
+  if ((flags & (GNMPPI_JAC_BF16 | GNMPPI_JAC_BF16X3)) && dtype != GNMPPI_F32) return GNMPPI_EINVAL;
+  if (!(lm_lambda >= 0.0) || !std::isfinite(lm_lambda)) return GNMPPI_EINVAL;
+  if (!aligned256(work)) return GNMPPI_EINVAL;
+  if (work_bytes < gnm::ggn_direction_bytes(dtype, m, n, K)) return GNMPPI_ENOSPACE;
+  if (static_cast<int64_t>(m + n) * 192 >= (int64_t{1} << 31)) return GNMPPI_EINVAL;
+  return status_of(gnm::launch_ggn_direction(dtype, m, n, K, R, ldr, r0, W, ldw, method, sigma2,
+                                             lm_lambda, dU, work, status, as_stream(stream)));
+}
+
 int gnmppi_ggn_step_noalloc(int32_t dtype, int32_t m, int32_t n, const void* J, int64_t ldj,
                             const void* r0, int64_t inc_r0, double lm_lambda, void* dU,
                             int32_t* status, void* stream) {
@@ -231,6 +267,6 @@ const char* gnmppi_status_string(int32_t status) {
   }
 }
 
-int32_t gnmppi_abi_version(void) { return 2; }
+int32_t gnmppi_abi_version(void) { return 3; }
 
 }  // extern "C"

@@ -30,7 +30,7 @@ constexpr int kCus = 256;  // MI355X compute units: the persistent grids are siz
 // Steps of one iteration in launch order; each is split by its shape class.
 enum Step {
   kSample, kGramW, kReduceG, kSweepG, kRollout, kNominal, kFused, kSplit, kContractS, kReduceS,
-  kJac, kGramH, kReduceH, kSweepH, kLine, kSteps
+  kGramH, kReduceH, kSweepH, kLine, kSteps
 };
 
 // Rollout modes (gnmppi_batch_tuning.rollout_mode): residuals through HBM
@@ -122,7 +122,7 @@ Plan make_plan(int count, const gnmppi_batch_instance* in, const gnmppi_batch_se
     d.seed = set->seed + static_cast<uint64_t>(i);
     pl.N_max = std::max(pl.N_max, d.N);
     tiles[kSample][i] = batch_sample_tiles(d.n, d.K);
-    tiles[kGramW][i] = batch_contract_row_blocks(d.n, 0) * d.gsplit;
+    tiles[kGramW][i] = batch_contract_row_blocks(d.n) * d.gsplit;
     tiles[kReduceG][i] = d.n;
     tiles[kSweepG][i] = 1;
     tiles[kRollout][i] = fused ? 0 : batch_rollout_tiles(d.M, d.K);
@@ -132,7 +132,6 @@ Plan make_plan(int count, const gnmppi_batch_instance* in, const gnmppi_batch_se
     tiles[kContractS][i] = fused ? 0 : batch_bf16_row_blocks(d.m) * d.nsplit;
     // one k-slice: the partial sum already is S (no reduction)
     tiles[kReduceS][i] = d.nsplit > 1 ? cdiv(d.m, 16) * cdiv(d.npad, 64) : 0;
-    tiles[kJac][i] = batch_contract_row_blocks(d.m, 1);
     tiles[kGramH][i] = d.hsplit;
     tiles[kReduceH][i] = d.n + 1;
     tiles[kSweepH][i] = 1;
@@ -149,7 +148,7 @@ Plan make_plan(int count, const gnmppi_batch_instance* in, const gnmppi_batch_se
   });
   auto cls_of = [&](Step s, const BatchInst& d) -> int {
     switch (s) {
-      case kGramW: case kContractS: case kJac: return cdiv(d.n, 16);
+      case kGramW: case kContractS: return cdiv(d.n, 16);
       case kSweepG: return cdiv(d.n, 16);
       case kGramH: case kSweepH: return cdiv(d.n + 1, 16);
       case kRollout: case kNominal: case kLine: return batch_chain_group(d.M);
@@ -207,7 +206,6 @@ Plan make_plan(int count, const gnmppi_batch_instance* in, const gnmppi_batch_se
     d.C = nullptr;  // the GN-MPPI step never reads the perturbed columns' costs
     d.r0 = reinterpret_cast<float*>(take(sizeof(float) * d.m));
     d.c0 = reinterpret_cast<float*>(take(sizeof(float)));
-    d.J = reinterpret_cast<float*>(take(sizeof(float) * static_cast<size_t>(d.m) * d.n));
     d.dU = reinterpret_cast<float*>(take(sizeof(float) * d.n));
     d.part = reinterpret_cast<float*>(
         take(sizeof(float) * static_cast<size_t>(d.nsplit) * d.m * d.npad));
@@ -248,7 +246,7 @@ hipError_t run_iteration(const Plan& pl, const gnmppi_problem& shared, char* bas
     hipError_t e = hipSuccess;
     switch (L.step) {
       case kSample: e = launch_batch_sample(inst, bl, sigma, static_cast<uint64_t>(it), st); break;
-      case kGramW: e = launch_batch_contract(0, L.cls, inst, bl, st); break;
+      case kGramW: e = launch_batch_contract(L.cls, inst, bl, st); break;
       case kReduceG: e = launch_batch_reduce_sym(0, inst, bl, 0.0, st); break;
       case kSweepG: e = launch_batch_sweep(0, L.cls, inst, bl, st); break;
       case kRollout: e = launch_batch_rollout(L.cls, inst, bl, shared, pl.N_max, st); break;
@@ -257,7 +255,6 @@ hipError_t run_iteration(const Plan& pl, const gnmppi_problem& shared, char* bas
       case kSplit: e = launch_batch_split_bf16(inst, bl, st); break;
       case kContractS: e = launch_batch_contract_bf16(L.cls, inst, bl, st); break;
       case kReduceS: e = launch_batch_reduce_rows(inst, bl, st); break;
-      case kJac: e = launch_batch_contract(1, L.cls, inst, bl, st); break;
       case kGramH: e = launch_batch_gram(L.cls, inst, bl, st); break;
       case kReduceH: e = launch_batch_reduce_sym(1, inst, bl, set.lm_lambda, st); break;
       case kSweepH: e = launch_batch_sweep(1, L.cls, inst, bl, st); break;

@@ -15,13 +15,14 @@
 namespace gnm {
 
 // One instance as the batched kernels see it (float32 chain, LS Jacobian with
-// the BF16x3 sample contraction, FP64 normal equations).
+// the BF16x3 sample contraction, FP64 normal equations; J = S G^{-1} is not
+// formed: the GGN system is solved in terms of S and G).
 struct BatchInst {
   int M, N, K, n, m;      // masses, horizon, samples, decisions 2N, residuals N (4M + 2)
   int npad, kpad;         // n rounded up to 16; K rounded up to 32
   int nsplit, split_len;  // k-slices of S = dR W^T
   int gsplit, gsplit_len; // k-slices of G = W W^T
-  int hchunk, hsplit;     // row chunks of [J r0]^T [J r0]
+  int hchunk, hsplit;     // row chunks of [S r0]^T [S r0]
   int64_t ldw, ldr;       // leading dimensions of W (n x K) and R (m x K)
   uint64_t seed;          // Philox key of this instance
   const float* x0;
@@ -36,7 +37,6 @@ struct BatchInst {
   float* C;       // null: the step needs no per-sample costs
   float* r0;
   float* c0;
-  float* J;       // m x n
   float* dU;      // n
   float* S;       // m x npad
   float* part;    // nsplit x m x npad (S partials)

@@ -18,13 +18,14 @@
 //      G^{-1} for the LS Jacobian and the GGN direction -(H^{-1} g) with no
 //      triangular solves.  A pivot at or below n 2^-52 max diag marks the
 //      matrix as not positive definite.
-//  * reduce_rows_kernel -- S (or, for MC, J = S / (K sigma^2)) as the sum of
-//      the k-split partials of the sample contraction; J = S G^{-1} then runs
-//      on the MFMA contraction kernel.
+//  * reduce_rows_kernel / reduce_rows_vec_kernel -- S (or, for MC,
+//      J = S / (K sigma^2)) as the sum of the k-split partials of the sample
+//      contraction; J = S G^{-1}, where it is formed, runs on the MFMA
+//      contraction kernel.
 //  * gram_pair_kernel / batch_gram_kernel<NT> -- the lower tiles of
-//      [J r0]^T [J r0] over a chunk of rows with the 16x16x4 f64 MFMA
-//      (products of float inputs are exact in double); one partial sum per
-//      chunk.
+//      [A r0]^T [A r0] (A = J, or S for the direction without J) over a
+//      chunk of rows with the 16x16x4 f64 MFMA (products of float inputs are
+//      exact in double); one partial sum per chunk.
 #include <mutex>
 #include <type_traits>
 
@@ -43,14 +44,32 @@ using f64x4 = double __attribute__((ext_vector_type(4)));
 
 // ---- partial-sum reduction -------------------------------------------------
 
+// (G G)[i][j] for the symmetric n x n G (row-major), in a fixed order, so
+// that entries (i, j) and (j, i) are bitwise equal.
+__device__ __forceinline__ double gram_square_entry(const double* __restrict__ G, int n, int i,
+                                                    int j) {
+  const double* gi = G + static_cast<int64_t>(i) * n;
+  double s0 = 0.0, s1 = 0.0;
+  int k = 0;
+  for (; k + 2 <= n; k += 2) {
+    s0 = fma(gi[k], G[static_cast<int64_t>(k) * n + j], s0);
+    s1 = fma(gi[k + 1], G[static_cast<int64_t>(k + 1) * n + j], s1);
+  }
+  if (k < n) s0 = fma(gi[k], G[static_cast<int64_t>(k) * n + j], s0);
+  return s0 + s1;
+}
+
 // out (P x P, full, symmetric) = sum_sp part[sp] (rows row0.., leading dim ldp),
 // reading only entries j <= i; diag_shift is added to the first npiv diagonal
-// entries.  grid.x = P (one row each), block = 256 >= P.
+// entries and, with Gsq != nullptr, lam_sq (Gsq Gsq)[i][j] (Gsq: npiv x npiv)
+// to the leading npiv x npiv block.  grid.x = P (one row each), block = 256 >= P.
 template <typename TP>
 __device__ __forceinline__ void reduce_sym_row(const TP* __restrict__ part, int nsplit,
                                                int64_t split_stride, int row0, int ldp, int P,
                                                int npiv, double diag_shift,
-                                               double* __restrict__ out, int i) {
+                                               double* __restrict__ out, int i,
+                                               const double* __restrict__ Gsq = nullptr,
+                                               double lam_sq = 0.0) {
   const int j = threadIdx.x;
   if (j > i) return;
   const TP* src = part + static_cast<int64_t>(row0 + i) * ldp + j;
@@ -73,6 +92,7 @@ __device__ __forceinline__ void reduce_sym_row(const TP* __restrict__ part, int 
     for (int u = 0; u < w; ++u) acc[u] += acc[u + w];
   double s = acc[0];
   if (i == j && i < npiv) s += diag_shift;
+  if (Gsq != nullptr && i < npiv) s += lam_sq * gram_square_entry(Gsq, npiv, i, j);
   out[static_cast<int64_t>(i) * P + j] = s;
   out[static_cast<int64_t>(j) * P + i] = s;
 }
@@ -81,13 +101,16 @@ template <typename TP>
 __global__ void __launch_bounds__(256) reduce_sym_kernel(const TP* __restrict__ part, int nsplit,
                                                          int64_t split_stride, int row0, int ldp,
                                                          int P, int npiv, double diag_shift,
-                                                         double* __restrict__ out) {
-  reduce_sym_row<TP>(part, nsplit, split_stride, row0, ldp, P, npiv, diag_shift, out, blockIdx.x);
+                                                         double* __restrict__ out,
+                                                         const double* __restrict__ Gsq,
+                                                         double lam_sq) {
+  reduce_sym_row<TP>(part, nsplit, split_stride, row0, ldp, P, npiv, diag_shift, out, blockIdx.x,
+                     Gsq, lam_sq);
 }
 
 // Batched: MODE 0 reduces the G = W W^T partials into Gsum (P = n), MODE 1
-// the [J r0]^T [J r0] partials into Hsum (P = n + 1, lambda on the first n
-// diagonal entries).  tile = row i.
+// the [S r0]^T [S r0] partials into Hsum (P = n + 1, plus lambda G^2 in the
+// leading n x n block).  tile = row i.
 template <int MODE>
 __global__ void __launch_bounds__(256) batch_reduce_sym_kernel(const BatchInst* __restrict__ inst,
                                                                BatchLaunch L, double lm_lambda) {
@@ -99,7 +122,8 @@ __global__ void __launch_bounds__(256) batch_reduce_sym_kernel(const BatchInst* 
                             b.n, 0.0, b.Gsum, it.tile);
     else
       reduce_sym_row<double>(b.hpart, b.hsplit, static_cast<int64_t>(b.n + 1) * (b.n + 1), 0,
-                             b.n + 1, b.n + 1, b.n, lm_lambda, b.Hsum, it.tile);
+                             b.n + 1, b.n + 1, b.n, 0.0, b.Hsum, it.tile,
+                             lm_lambda > 0.0 ? b.Gsum : nullptr, lm_lambda);
   }
 }
 
@@ -138,45 +162,72 @@ __global__ void __launch_bounds__(256) reduce_rows_kernel(const T* __restrict__ 
                        blockIdx.y);
 }
 
-// Batched S = sum of the k-slices over all npad columns (the padding columns
-// of every slice are zero): tile = row group * ceil(npad / 64) + column
-// group, 16 rows x 64 columns per block, four columns per thread with 16-byte
-// loads, eight slices in flight, summed in slice order in double precision.
-__global__ void __launch_bounds__(256) batch_reduce_rows_kernel(const BatchInst* __restrict__ inst,
-                                                                BatchLaunch L) {
+// Sum of the k-slices (rows x npad each, slice stride rows * npad) over all
+// npad columns, in slice order in double precision: rows i < m go to the FP32
+// S (scaled by `scale`), rows m <= i < rows -- the rows of G = W W^T when the
+// contraction carried them -- to the double ng x ng Gsum (columns < ng).
+// tile = row group * ceil(npad / 64) + column group, 16 rows x 64 columns per
+// block, four columns per thread with 16-byte loads, eight slices in flight.
+__device__ __forceinline__ void reduce_rows_vec(const float* __restrict__ part, int nsplit,
+                                                int rows, int m, int npad, double scale,
+                                                float* __restrict__ S, int ng,
+                                                double* __restrict__ Gsum, int tile) {
   using f32x4 = float __attribute__((ext_vector_type(4)));
-  for (int w = blockIdx.x; w < L.count; w += gridDim.x) {
-    const BatchItem it = L.items[w];
-    const BatchInst& b = inst[it.inst];
-    const int xb = (b.npad + 63) / 64;
-    const int i = (it.tile / xb) * 16 + (threadIdx.x >> 4);
-    const int c = (it.tile % xb) * 64 + 4 * (threadIdx.x & 15);
-    if (i >= b.m || c >= b.npad) continue;
-    const int64_t stride = static_cast<int64_t>(b.m) * b.npad;
-    const float* src = b.part + static_cast<int64_t>(i) * b.npad + c;
-    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    constexpr int U = 8;
-    for (int sp = 0; sp < b.nsplit; sp += U) {
-      f32x4 v[U];
+  const int xb = (npad + 63) / 64;
+  const int i = (tile / xb) * 16 + (threadIdx.x >> 4);
+  const int c = (tile % xb) * 64 + 4 * (threadIdx.x & 15);
+  if (i >= rows || c >= npad) return;
+  const int64_t stride = static_cast<int64_t>(rows) * npad;
+  const float* src = part + static_cast<int64_t>(i) * npad + c;
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  constexpr int U = 8;
+  for (int sp = 0; sp < nsplit; sp += U) {
+    f32x4 v[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        v[u] = sp + u < b.nsplit ? *reinterpret_cast<const f32x4*>(src + (sp + u) * stride)
-                                 : f32x4{0, 0, 0, 0};
+    for (int u = 0; u < U; ++u)
+      v[u] = sp + u < nsplit ? *reinterpret_cast<const f32x4*>(src + (sp + u) * stride)
+                             : f32x4{0, 0, 0, 0};
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        a0 += static_cast<double>(v[u][0]);
-        a1 += static_cast<double>(v[u][1]);
-        a2 += static_cast<double>(v[u][2]);
-        a3 += static_cast<double>(v[u][3]);
-      }
+    for (int u = 0; u < U; ++u) {
+      a0 += static_cast<double>(v[u][0]);
+      a1 += static_cast<double>(v[u][1]);
+      a2 += static_cast<double>(v[u][2]);
+      a3 += static_cast<double>(v[u][3]);
     }
-    *reinterpret_cast<f32x4*>(b.S + static_cast<int64_t>(i) * b.npad + c) =
-        f32x4{static_cast<float>(a0), static_cast<float>(a1), static_cast<float>(a2),
-              static_cast<float>(a3)};
+  }
+  if (i < m) {
+    *reinterpret_cast<f32x4*>(S + static_cast<int64_t>(i) * npad + c) =
+        f32x4{static_cast<float>(a0 * scale), static_cast<float>(a1 * scale),
+              static_cast<float>(a2 * scale), static_cast<float>(a3 * scale)};
+  } else {
+    double* g = Gsum + static_cast<int64_t>(i - m) * ng + c;
+    if (c + 0 < ng) g[0] = a0;
+    if (c + 1 < ng) g[1] = a1;
+    if (c + 2 < ng) g[2] = a2;
+    if (c + 3 < ng) g[3] = a3;
   }
 }
 
-// ---- [J r0]^T [J r0] with the f64 MFMA ------------------------------------------
+__global__ void __launch_bounds__(256) reduce_rows_vec_kernel(const float* __restrict__ part,
+                                                              int nsplit, int rows, int m,
+                                                              int npad, double scale,
+                                                              float* __restrict__ S, int ng,
+                                                              double* __restrict__ Gsum) {
+  reduce_rows_vec(part, nsplit, rows, m, npad, scale, S, ng, Gsum, blockIdx.x);
+}
+
+// Batched: the slices of every instance (the padding columns of every slice
+// are zero).
+__global__ void __launch_bounds__(256) batch_reduce_rows_kernel(const BatchInst* __restrict__ inst,
+                                                                BatchLaunch L) {
+  for (int w = blockIdx.x; w < L.count; w += gridDim.x) {
+    const BatchItem it = L.items[w];
+    const BatchInst& b = inst[it.inst];
+    reduce_rows_vec(b.part, b.nsplit, b.m, b.m, b.npad, 1.0, b.S, 0, nullptr, it.tile);
+  }
+}
+
+// ---- [A r0]^T [A r0] with the f64 MFMA (A = J, or S) ------------------------------
 
 // f64 16x16x4 MFMA: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
 // accumulator element j of lane l is D[4 j + l / 16][l % 16].
@@ -242,14 +293,14 @@ __device__ __forceinline__ void gram_chunk(int m, int n, const T* __restrict__ J
       }
 }
 
-// Batched [J r0]^T [J r0] partials; tile = row chunk.
+// Batched [S r0]^T [S r0] partials; tile = row chunk.
 template <int NT>
 __global__ void __launch_bounds__(256) batch_gram_kernel(const BatchInst* __restrict__ inst,
                                                          BatchLaunch L) {
   for (int w = blockIdx.x; w < L.count; w += gridDim.x) {
     const BatchItem it = L.items[w];
     const BatchInst& b = inst[it.inst];
-    gram_chunk<float, NT>(b.m, b.n, b.J, b.n, b.r0, 1, b.hchunk, b.n + 1, b.hpart, it.tile);
+    gram_chunk<float, NT>(b.m, b.n, b.S, b.npad, b.r0, 1, b.hchunk, b.n + 1, b.hpart, it.tile);
   }
 }
 
@@ -394,7 +445,7 @@ hipError_t gram_inverse_typed(const JacPlan& pl, int n, int K, const T* W, int64
   double* Gsum = reinterpret_cast<double*>(wk + pl.gsum_off);
   T* Ginv = reinterpret_cast<T*>(wk + pl.ginv_off);
   hipLaunchKernelGGL(reduce_sym_kernel<T>, dim3(n), dim3(256), 0, st, part, nsplit, split_stride,
-                     row0, pl.npad, n, n, 0.0, Gsum);
+                     row0, pl.npad, n, n, 0.0, Gsum, static_cast<const double*>(nullptr), 0.0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   (void)K;
@@ -529,7 +580,8 @@ hipError_t launch_ggn(int dtype, int m, int n, const void* J, int64_t ldj, const
   if (e != hipSuccess) return e;
   const int64_t split_stride = static_cast<int64_t>(g.P) * g.P;
   hipLaunchKernelGGL(reduce_sym_kernel<double>, dim3(g.P), dim3(256), 0, st, part, g.nsplit,
-                     split_stride, 0, g.P, g.P, n, lm_lambda, Hsum);
+                     split_stride, 0, g.P, g.P, n, lm_lambda, Hsum,
+                     static_cast<const double*>(nullptr), 0.0);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (dtype == GNMPPI_F32)
@@ -537,6 +589,116 @@ hipError_t launch_ggn(int dtype, int m, int n, const void* J, int64_t ldj, const
                                status, GNMPPI_ENOTPD, st);
   return launch_sweep(g.P, n, kSweepDirection, Hsum, nullptr, 0, static_cast<double*>(dU),
                               status, GNMPPI_ENOTPD, st);
+}
+
+// ---- the GGN direction without forming J ------------------------------------
+
+// With J = S A (LS: A = G^{-1}; MC: A = I / (K sigma2)) and B = A^{-1},
+// J^T J + lambda I = A (S^T S + lambda B^2) A and J^T r0 = A S^T r0, so the
+// GGN direction is dU = B y with (S^T S + lambda B^2) y = -S^T r0.  LS runs
+// that system: the normal matrix of [S r0] (plus lambda G^2), the sweep, and
+// B = G applied to y inside the sweep, so J = S G^{-1} (an m x n x n
+// contraction) is never formed.  Without a ready G the sample contraction
+// carries the n rows of W as extra rows of its A operand, so G comes out of
+// the same launch and the same slice reduction as S.  MC forms
+// J = S / (K sigma2) in the slice reduction, then the plain GGN step.
+// Workspace: the Jacobian workspace followed by the GGN workspace.
+size_t ggn_direction_bytes(int dtype, int m, int n, int K) {
+  return jacobian_plan(dtype, m, n, K, GNMPPI_JAC_LS).total + ggn_plan(dtype, m, n).total;
+}
+
+template <typename T>
+hipError_t ggn_direction_typed(int m, int n, int K, const T* R, int64_t ldr, const T* r0,
+                               const T* W, int64_t ldw, int method, double sigma2,
+                               double lm_lambda, T* dU, void* work, int32_t* status,
+                               hipStream_t st) {
+  const int dtype = sizeof(T) == 4 ? GNMPPI_F32 : GNMPPI_F64;
+  // the offsets of the regions (partials, G, S) and the workspace size
+  const JacPlan pl = jacobian_plan(dtype, m, n, K, GNMPPI_JAC_LS);
+  const int base = method & 0xff;
+  const bool ls = base == GNMPPI_JAC_LS;
+  const bool with_gram = ls && (method & GNMPPI_JAC_GRAM_READY) == 0;
+  const bool s_only = (method & GNMPPI_JAC_S_ONLY) != 0;
+  const bool apply_only = (method & GNMPPI_JAC_APPLY_ONLY) != 0;
+  const int bf16_terms = (method & GNMPPI_JAC_BF16X3) ? 3 : (method & GNMPPI_JAC_BF16) ? 1 : 0;
+  // rows of each k-slice: S, then (with_gram) G; the partial-sum region
+  // holds the largest split count of every row set, so these fit
+  const int rows = with_gram ? m + n : m;
+  int nsplit = 0, split_len = 0;
+  if (bf16_terms)
+    bf16_split_plan(rows, K, nsplit, split_len);
+  else
+    split_plan(rows, K, sizeof(T) == 4 ? 32 : 16, contract_kw(sizeof(T), n), nsplit, split_len);
+  char* wk = static_cast<char*>(work);
+  T* part = reinterpret_cast<T*>(wk);
+  const int64_t split_stride = static_cast<int64_t>(rows) * pl.npad;
+  double* Gsum = reinterpret_cast<double*>(wk + pl.gsum_off);
+  hipError_t e = hipSuccess;
+  if (!apply_only) {
+    if constexpr (sizeof(T) == 4) {
+      if (bf16_terms)
+        e = launch_contract_bf16(bf16_terms, m, n, K, R, ldr, r0, W, ldw, nsplit, split_len, part,
+                                 pl.npad, st, with_gram);
+    }
+    if (!bf16_terms) {
+      // A = [R - r0 1^T; W] (the W rows only with_gram), B = W
+      ContractArgs<T> c1{m, rows, n, K, R, ldr, r0, W, ldw, W, ldw, split_len,
+                         part, pl.npad, split_stride, pl.npad};
+      e = launch_contract(c1, nsplit, st);
+    }
+    if (e != hipSuccess || s_only) return e;
+  }
+  // S (LS) or J (MC) from the slices, and G (with_gram)
+  T* S = reinterpret_cast<T*>(wk + pl.s_off);
+  const double scale = ls ? 1.0 : 1.0 / (static_cast<double>(K) * sigma2);
+  if constexpr (sizeof(T) == 4) {
+    hipLaunchKernelGGL(reduce_rows_vec_kernel, dim3(((rows + 15) / 16) * ((pl.npad + 63) / 64)),
+                       dim3(256), 0, st, part, nsplit, rows, m, pl.npad, scale, S, n, Gsum);
+  } else {
+    const dim3 rgrid((n + 63) / 64, (m + 3) / 4);
+    hipLaunchKernelGGL(reduce_rows_kernel<T>, rgrid, dim3(256), 0, st, part, nsplit,
+                       split_stride, pl.npad, m, n, scale, S, static_cast<int64_t>(pl.npad),
+                       static_cast<int32_t*>(nullptr));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (with_gram)
+      hipLaunchKernelGGL(reduce_sym_kernel<T>, dim3(n), dim3(256), 0, st, part, nsplit,
+                         split_stride, m, pl.npad, n, n, 0.0, Gsum,
+                         static_cast<const double*>(nullptr), 0.0);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // normal matrix of [S r0] (of [J r0] for MC, lambda on its diagonal)
+  const GgnPlan g = ggn_plan(dtype, m, n);
+  char* gw = wk + pl.total;
+  double* gpart = reinterpret_cast<double*>(gw);
+  double* Hsum = reinterpret_cast<double*>(gw + g.part_bytes);
+  e = launch_gram_pairs<T>(g.tiles, g.nsplit, st, m, n, S, pl.npad, r0, 1, g.P, gpart);
+  if (e != hipSuccess) return e;
+  // LS: + lambda G^2 (B = G); MC: + lambda on the diagonal
+  hipLaunchKernelGGL(reduce_sym_kernel<double>, dim3(g.P), dim3(256), 0, st, gpart, g.nsplit,
+                     static_cast<int64_t>(g.P) * g.P, 0, g.P, g.P, n, ls ? 0.0 : lm_lambda, Hsum,
+                     ls && lm_lambda > 0.0 ? static_cast<const double*>(Gsum) : nullptr,
+                     lm_lambda);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_sweep(g.P, n, kSweepDirection, Hsum, nullptr, 0, dU, status, GNMPPI_ENOTPD, st,
+                      ls ? static_cast<const double*>(Gsum) : nullptr, static_cast<int64_t>(n));
+}
+
+hipError_t launch_ggn_direction(int dtype, int m, int n, int K, const void* R, int64_t ldr,
+                                const void* r0, const void* W, int64_t ldw, int method,
+                                double sigma2, double lm_lambda, void* dU, void* work,
+                                int32_t* status, hipStream_t st) {
+  if (dtype == GNMPPI_F32)
+    return ggn_direction_typed<float>(m, n, K, static_cast<const float*>(R), ldr,
+                                      static_cast<const float*>(r0), static_cast<const float*>(W),
+                                      ldw, method, sigma2, lm_lambda, static_cast<float*>(dU),
+                                      work, status, st);
+  return ggn_direction_typed<double>(m, n, K, static_cast<const double*>(R), ldr,
+                                     static_cast<const double*>(r0), static_cast<const double*>(W),
+                                     ldw, method, sigma2, lm_lambda, static_cast<double*>(dU),
+                                     work, status, st);
 }
 
 // ---- the GGN step without a caller workspace ----------------------------------

@@ -204,35 +204,25 @@ __global__ void __launch_bounds__(256) contract_kernel(ContractArgs<T> a) {
   contract_block<T, NT, VEC, KW>(a, blockIdx.x, blockIdx.y, contract_smem);
 }
 
-// Batched float32 contractions of an iteration: MODE 0 forms the G = W W^T
-// partials, MODE 1 the Jacobian J = S G^{-1}.  tile = by * row_blocks + bx.
-template <int MODE>
-__device__ __forceinline__ ContractArgs<float> batch_contract_args(const BatchInst& b) {
-  if constexpr (MODE == 0)
-    return ContractArgs<float>{b.n, b.n, b.n, b.K, b.W, b.ldw, nullptr, nullptr, 0, b.W, b.ldw,
-                               b.gsplit_len, b.gpart, b.npad,
-                               static_cast<int64_t>(b.n) * b.npad, b.npad};
-  else
-    return ContractArgs<float>{b.m, b.m, b.n, b.n, b.S, b.npad, nullptr, nullptr, 0, b.Ginv,
-                               b.npad, b.n, b.J, b.n, 0, b.n};
+// Batched G = W W^T partials of an iteration (K = samples, few rows): four
+// waves split the k-steps of one 16-row tile.  tile = by * row_blocks + bx.
+__device__ __forceinline__ ContractArgs<float> batch_gram_w_args(const BatchInst& b) {
+  return ContractArgs<float>{b.n, b.n, b.n, b.K, b.W, b.ldw, nullptr, nullptr, 0, b.W, b.ldw,
+                             b.gsplit_len, b.gpart, b.npad,
+                             static_cast<int64_t>(b.n) * b.npad, b.npad};
 }
 
-// G (K = samples, few rows): four waves split the k-steps of one 16-row tile;
-// J (K' = n, many rows): one wave per 16-row tile, four tiles per block.
-template <int MODE>
-constexpr int batch_contract_kw() { return MODE == 0 ? 4 : 1; }
-
-template <int NT, int MODE>
+template <int NT>
 __global__ void __launch_bounds__(256) batch_contract_kernel(const BatchInst* __restrict__ inst,
                                                              BatchLaunch L) {
-  constexpr int KW = batch_contract_kw<MODE>();
+  constexpr int KW = 4;
   extern __shared__ unsigned char contract_smem[];
   for (int w = blockIdx.x; w < L.count; w += gridDim.x) {
     const BatchItem it = L.items[w];
-    const ContractArgs<float> a = batch_contract_args<MODE>(inst[it.inst]);
+    const ContractArgs<float> a = batch_gram_w_args(inst[it.inst]);
     const int rb = (a.rows + 64 / KW - 1) / (64 / KW);
     contract_block<float, NT, true, KW>(a, it.tile % rb, it.tile / rb, contract_smem);
-    if constexpr (KW > 1) __syncthreads();  // the next item reuses the LDS
+    __syncthreads();  // the next item reuses the LDS
   }
 }
 
@@ -334,12 +324,15 @@ __global__ void __launch_bounds__(256) batch_split_bf16_kernel(const BatchInst* 
 // Each thread then loads 8-value pieces of W rows (two 16-byte loads when
 // wvec: ldw % 4 == 0 and Wf 16-byte aligned) and writes both planes.
 using f32x8 = float __attribute__((ext_vector_type(8)));
+// With WF32, rows m .. arows - 1 of A are the rows of W (Wf, no r0 shift),
+// so that the same launch also forms the partials of G = W W^T.
 template <int TERMS, int NT, int TM, bool VEC, bool WF32 = false>
 __device__ __forceinline__ void contract_bf16_block(
     int m, int n, int K, const float* __restrict__ R, int64_t ldr, const float* __restrict__ r0,
     const __bf16* __restrict__ Bh, const __bf16* __restrict__ Bl, int kpad, int split_len,
     float* __restrict__ part, int npad, int bx, int by, const float* __restrict__ Wf = nullptr,
-    int64_t ldw = 0, bool wvec = false) {
+    int64_t ldw = 0, bool wvec = false, int arows = -1) {
+  if (!WF32 || arows < m) arows = m;
   constexpr int PLANES = TERMS == 3 ? 2 : 1;
   constexpr int NCOL = 16 * NT;
   // pieces per stage: 16-byte bf16 pieces of each plane, or 8-value FP32
@@ -361,8 +354,13 @@ __device__ __forceinline__ void contract_bf16_block(
 #pragma unroll
   for (int t = 0; t < TM; ++t) {
     const int row = row_base + 16 * t + r16;
-    arow[t] = R + (row < m ? row : 0) * ldr;
-    asub[t] = row < m ? r0[row] : 0.0f;
+    if (row < m || row >= arows) {
+      arow[t] = R + (row < m ? row : 0) * ldr;
+      asub[t] = row < m ? r0[row] : 0.0f;
+    } else {
+      arow[t] = Wf + static_cast<int64_t>(row - m) * ldw;
+      asub[t] = 0.0f;
+    }
   }
   // the B pieces this thread copies: piece c -> (plane, column, k-group),
   // k-group fastest so that 8 neighbouring threads read one 128-byte run
@@ -512,13 +510,13 @@ __device__ __forceinline__ void contract_bf16_block(
       __syncthreads();
     }
   }
-  float* out = part + static_cast<int64_t>(by) * m * npad;
+  float* out = part + static_cast<int64_t>(by) * arows * npad;
 #pragma unroll
   for (int t = 0; t < TM; ++t)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int row = row_base + 16 * t + 4 * kq + j;
-      if (row < m)
+      if (row < arows)
 #pragma unroll
         for (int tn = 0; tn < NT; ++tn) out[row * npad + 16 * tn + r16] = acc[t][tn][j];
     }
@@ -528,9 +526,10 @@ template <int TERMS, int NT, int TM, bool VEC>
 __global__ void __launch_bounds__(256) contract_bf16_kernel(
     int m, int n, int K, const float* __restrict__ R, int64_t ldr, const float* __restrict__ r0,
     const float* __restrict__ Wf, int64_t ldw, bool wvec, int split_len, float* __restrict__ part,
-    int npad) {
+    int npad, int arows) {
   contract_bf16_block<TERMS, NT, TM, VEC, true>(m, n, K, R, ldr, r0, nullptr, nullptr, 0, split_len,
-                                                part, npad, blockIdx.x, blockIdx.y, Wf, ldw, wvec);
+                                                part, npad, blockIdx.x, blockIdx.y, Wf, ldw, wvec,
+                                                arows);
 }
 
 // Batched S = (R - r0 1^T) W^T partials, BF16x3; tile = split * row_blocks + row block.
@@ -551,11 +550,11 @@ __global__ void __launch_bounds__(256) batch_contract_bf16_kernel(const BatchIns
 template <int TERMS, bool VEC>
 hipError_t bf16_dispatch(int nt, dim3 grid, hipStream_t st, int m, int n, int K, const float* R,
                          int64_t ldr, const float* r0, const float* W, int64_t ldw, bool wvec,
-                         int split_len, float* part, int npad) {
+                         int split_len, float* part, int npad, int arows) {
 #define GNM_BF_CASE(NT)                                                                        \
   case NT:                                                                                     \
     hipLaunchKernelGGL((contract_bf16_kernel<TERMS, NT, kBf16RowTiles, VEC>), grid, dim3(256), 0, \
-                       st, m, n, K, R, ldr, r0, W, ldw, wvec, split_len, part, npad);          \
+                       st, m, n, K, R, ldr, r0, W, ldw, wvec, split_len, part, npad, arows);   \
     break;
   switch (nt) {
     GNM_BF_CASE(1) GNM_BF_CASE(2) GNM_BF_CASE(3) GNM_BF_CASE(4) GNM_BF_CASE(5) GNM_BF_CASE(6)
@@ -582,24 +581,18 @@ hipError_t launch_contract(const ContractArgs<double>& a, int nsplit, hipStream_
   return contract_typed(a, nsplit, st);
 }
 
-int batch_contract_row_blocks(int rows, int mode) {
-  return mode == 0 ? (rows + 15) / 16 : (rows + 63) / 64;
-}
+int batch_contract_row_blocks(int rows) { return (rows + 15) / 16; }
 int batch_bf16_row_blocks(int m) {
   return (m + 64 * kBatchBf16RowTiles - 1) / (64 * kBatchBf16RowTiles);
 }
 
-hipError_t launch_batch_contract(int mode, int nt, const BatchInst* inst, const BatchLaunch& L,
+hipError_t launch_batch_contract(int nt, const BatchInst* inst, const BatchLaunch& L,
                                  hipStream_t st) {
   if (L.count == 0) return hipSuccess;
 #define GNM_BC_CASE(NT)                                                                          \
   case NT:                                                                                       \
-    if (mode == 0)                                                                               \
-      hipLaunchKernelGGL((batch_contract_kernel<NT, 0>), dim3(L.blocks), dim3(256),             \
-                         (split_lds_bytes<float, NT>()), st, inst, L);                          \
-    else                                                                                         \
-      hipLaunchKernelGGL((batch_contract_kernel<NT, 1>), dim3(L.blocks), dim3(256), 0, st,      \
-                         inst, L);                                                              \
+    hipLaunchKernelGGL((batch_contract_kernel<NT>), dim3(L.blocks), dim3(256),                  \
+                       (split_lds_bytes<float, NT>()), st, inst, L);                            \
     break;
   switch (nt) {
     GNM_BC_CASE(1) GNM_BC_CASE(2) GNM_BC_CASE(3) GNM_BC_CASE(4) GNM_BC_CASE(5) GNM_BC_CASE(6)
@@ -637,20 +630,24 @@ hipError_t launch_batch_contract_bf16(int nt, const BatchInst* inst, const Batch
 
 hipError_t launch_contract_bf16(int terms, int m, int n, int K, const float* R, int64_t ldr,
                                 const float* r0, const float* W, int64_t ldw, int nsplit,
-                                int split_len, float* part, int npad, hipStream_t st) {
-  dim3 grid((m + 64 * kBf16RowTiles - 1) / (64 * kBf16RowTiles), nsplit);
+                                int split_len, float* part, int npad, hipStream_t st,
+                                bool with_gram) {
+  const int arows = with_gram ? m + n : m;
+  dim3 grid((arows + 64 * kBf16RowTiles - 1) / (64 * kBf16RowTiles), nsplit);
   const int nt = (n + 15) / 16;
-  const bool vec = (ldr % 4 == 0) && (reinterpret_cast<uintptr_t>(R) % 16 == 0);
   const bool wvec = (ldw % 4 == 0) && (reinterpret_cast<uintptr_t>(W) % 16 == 0);
+  // the vector A loads need aligned rows of R (and of W when it is part of A)
+  const bool vec = (ldr % 4 == 0) && (reinterpret_cast<uintptr_t>(R) % 16 == 0) &&
+                   (!with_gram || wvec);
   if (terms == 3)
     return vec ? bf16_dispatch<3, true>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, wvec, split_len,
-                                        part, npad)
+                                        part, npad, arows)
                : bf16_dispatch<3, false>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, wvec,
-                                         split_len, part, npad);
+                                         split_len, part, npad, arows);
   return vec ? bf16_dispatch<1, true>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, wvec, split_len,
-                                      part, npad)
+                                      part, npad, arows)
              : bf16_dispatch<1, false>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, wvec, split_len,
-                                       part, npad);
+                                       part, npad, arows);
 }
 
 }  // namespace gnm

@@ -64,10 +64,13 @@ hipError_t launch_contract(const ContractArgs<float>& a, int nsplit, hipStream_t
 hipError_t launch_contract(const ContractArgs<double>& a, int nsplit, hipStream_t st);
 
 // BF16 MFMA contraction S = (R - r0 1^T) W^T (terms = 1 or 3); it reads the
-// FP32 W and rounds / splits it on its way into LDS.
+// FP32 W and rounds / splits it on its way into LDS.  with_gram: A also
+// holds the n rows of W, so each k-slice (m + n rows) carries G = W W^T
+// below S.
 hipError_t launch_contract_bf16(int terms, int m, int n, int K, const float* R, int64_t ldr,
                                 const float* r0, const float* W, int64_t ldw, int nsplit,
-                                int split_len, float* part, int npad, hipStream_t st);
+                                int split_len, float* part, int npad, hipStream_t st,
+                                bool with_gram = false);
 
 // Symmetric sweep of an SPD matrix M (P x P, full, double) over its first
 // npiv pivots (sweep.hpp): kSweepInverse writes the inverse of the leading
@@ -75,10 +78,14 @@ hipError_t launch_contract_bf16(int terms, int m, int n, int K, const float* R, 
 // -(H^{-1} g) of M = [[H, g], [g^T, c]] into dir_out.  A failed pivot writes
 // fail_code to *status (else GNMPPI_OK).  P <= 208.
 enum SweepOut { kSweepInverse = 0, kSweepDirection = 1 };
+// Direction mode with post != nullptr writes post * y (post: symmetric
+// npiv x npiv double, leading dimension ldp) in place of the direction y.
 hipError_t launch_sweep(int P, int npiv, int mode, const double* M, float* inv_out, int64_t ldo,
-                        float* dir_out, int32_t* status, int fail_code, hipStream_t st);
+                        float* dir_out, int32_t* status, int fail_code, hipStream_t st,
+                        const double* post = nullptr, int64_t ldp = 0);
 hipError_t launch_sweep(int P, int npiv, int mode, const double* M, double* inv_out, int64_t ldo,
-                        double* dir_out, int32_t* status, int fail_code, hipStream_t st);
+                        double* dir_out, int32_t* status, int fail_code, hipStream_t st,
+                        const double* post = nullptr, int64_t ldp = 0);
 
 // Jacobian reconstruction; `work` holds the GEMM partials, G, G^{-1} and S.
 struct JacPlan {
@@ -104,6 +111,14 @@ hipError_t launch_jacobian(int dtype, int m, int n, int K, const void* R, int64_
                            const void* r0, const void* W, int64_t ldw, int method,
                            double sigma2, void* J, int64_t ldj, void* work,
                            int32_t* status, hipStream_t st);
+
+// The GGN direction for the J of launch_jacobian without forming J; the
+// workspace is the Jacobian workspace followed by the GGN workspace.
+size_t ggn_direction_bytes(int dtype, int m, int n, int K);
+hipError_t launch_ggn_direction(int dtype, int m, int n, int K, const void* R, int64_t ldr,
+                                const void* r0, const void* W, int64_t ldw, int method,
+                                double sigma2, double lm_lambda, void* dU, void* work,
+                                int32_t* status, hipStream_t st);
 
 struct GgnPlan {
   int nsplit;        // row chunks of the J^T J contraction
@@ -148,9 +163,9 @@ hipError_t launch_batch_fused(const BatchInst* inst, const BatchLaunch& L,
 hipError_t launch_batch_line_search(int G, const BatchInst* inst, const BatchLaunch& L,
                                     const gnmppi_problem& shared, int n_alpha, int N_max,
                                     hipStream_t st);
-int batch_contract_row_blocks(int rows, int mode);
+int batch_contract_row_blocks(int rows);  // 16-row tiles of the G = W W^T contraction
 int batch_bf16_row_blocks(int m);
-hipError_t launch_batch_contract(int mode, int nt, const BatchInst* inst, const BatchLaunch& L,
+hipError_t launch_batch_contract(int nt, const BatchInst* inst, const BatchLaunch& L,
                                  hipStream_t st);
 hipError_t launch_batch_split_bf16(const BatchInst* inst, const BatchLaunch& L, hipStream_t st);
 hipError_t launch_batch_contract_bf16(int nt, const BatchInst* inst, const BatchLaunch& L,

@@ -339,7 +339,7 @@ template <int R, int W, typename TO>
 __device__ __forceinline__ bool sweep_update_role(const SweepLds& L, const double* __restrict__ M,
                                                   int P, int npiv, bool solve_only, int lane,
                                                   TO* __restrict__ inv_out, int64_t ldo,
-                                                  TO* __restrict__ dir_out) {
+                                                  TO* __restrict__ dir_out, double* ydir) {
   constexpr int LD = kSweepLd, TL = 16 * LD, NT = R * (R + 1) / 2;
   constexpr int NS = sweep_slots<R>(W);
   const int li = lane & 15, q = lane >> 4;
@@ -464,23 +464,33 @@ __device__ __forceinline__ bool sweep_update_role(const SweepLds& L, const doubl
         }
       });
   } else {
-    // the augmented row npiv holds H^{-1} g in columns j < npiv
+    // the augmented row npiv holds H^{-1} g in columns j < npiv; with a
+    // post-multiplication the direction goes to LDS (ydir) first
     tiles([&](auto rc, auto cc, auto sc) {
       constexpr int r = decltype(rc)::value, c = decltype(cc)::value, s = decltype(sc)::value;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int i = 16 * r + 4 * e + q, j = 16 * c + li;
-        if (i == npiv && j < npiv) dir_out[j] = ok ? static_cast<TO>(-acc[s][e]) : TO(0);
+        if (i == npiv && j < npiv) {
+          if (ydir != nullptr)
+            ydir[j] = -acc[s][e];
+          else
+            dir_out[j] = ok ? static_cast<TO>(-acc[s][e]) : TO(0);
+        }
       }
     });
   }
   return ok;
 }
 
+// With post != nullptr (direction mode only) the direction y = -H^{-1} g is
+// multiplied by the symmetric npiv x npiv matrix `post` (row-major, leading
+// dimension ldp) before it is written: dir_out = post y.
 template <int R, typename TO>
 __device__ __forceinline__ void sweep_matrix(
     const double* __restrict__ M, int P, int npiv, int mode, TO* __restrict__ inv_out, int64_t ldo,
-    TO* __restrict__ dir_out, int32_t* status, int fail_code) {
+    TO* __restrict__ dir_out, int32_t* status, int fail_code, const double* __restrict__ post,
+    int64_t ldp) {
   constexpr int LD = kSweepLd, TL = 16 * LD;
   __shared__ __attribute__((aligned(16))) double pan[2 * 16 * R * LD];
   __shared__ __attribute__((aligned(16))) double ybufw[16 * R * LD];
@@ -488,6 +498,7 @@ __device__ __forceinline__ void sweep_matrix(
   __shared__ __attribute__((aligned(16))) double tiles16[7 * TL];
   __shared__ double wmax[kSweepWaves];
   __shared__ int diag_ok[2];
+  __shared__ double ydir[16 * R];
   const SweepLds L{pan,           ybufw,          ybufp,    tiles16,  tiles16 + 2 * TL,
                    tiles16 + 4 * TL, tiles16 + 6 * TL, wmax, diag_ok, 16 * R * LD};
   const int lane = threadIdx.x & (kWave - 1);
@@ -496,27 +507,69 @@ __device__ __forceinline__ void sweep_matrix(
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const bool solve_only = mode == kSweepDirection;
   TO* inv = mode == kSweepInverse ? inv_out : nullptr;
+  const bool postmul = solve_only && post != nullptr;
+  double* yd = postmul ? ydir : nullptr;
   bool ok;
   if (wave == 0)
     ok = sweep_pivot_role<R>(L, npiv, lane);
   else if (wave == 1)
-    ok = sweep_update_role<R, 1, TO>(L, M, P, npiv, solve_only, lane, inv, ldo, dir_out);
+    ok = sweep_update_role<R, 1, TO>(L, M, P, npiv, solve_only, lane, inv, ldo, dir_out, yd);
   else if (wave == 2)
-    ok = sweep_update_role<R, 2, TO>(L, M, P, npiv, solve_only, lane, inv, ldo, dir_out);
+    ok = sweep_update_role<R, 2, TO>(L, M, P, npiv, solve_only, lane, inv, ldo, dir_out, yd);
   else
-    ok = sweep_update_role<R, 3, TO>(L, M, P, npiv, solve_only, lane, inv, ldo, dir_out);
+    ok = sweep_update_role<R, 3, TO>(L, M, P, npiv, solve_only, lane, inv, ldo, dir_out, yd);
+  if (postmul) {
+    __syncthreads();
+    // dir_out[i] = sum_j post[i][j] y_j: wave w takes rows w, w + 4, ...,
+    // lane l columns l, l + 64, ...; the loads of kRows rows are issued
+    // together (one memory round trip per batch of rows, not per row) and
+    // each row's products are summed over the wave by a fixed butterfly
+    constexpr int kChunks = (16 * R + kWave - 1) / kWave;
+    constexpr int kRowsPerWave = (16 * R + kSweepWaves - 1) / kSweepWaves;
+    constexpr int kRowsMax = kChunks >= 4 ? 8 : 32 / kChunks;
+    constexpr int kRows = kRowsMax < kRowsPerWave ? kRowsMax : kRowsPerWave;
+    double yv[kChunks];
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+      const int j = lane + kWave * c;
+      yv[c] = j < npiv ? ydir[j] : 0.0;
+    }
+#pragma unroll 1
+    for (int r0 = 0; r0 < kRowsPerWave; r0 += kRows) {
+      double v[kRows][kChunks];
+#pragma unroll
+      for (int b = 0; b < kRows; ++b) {
+        const int i = min(wave + kSweepWaves * (r0 + b), npiv - 1);
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c)
+          v[b][c] = post[static_cast<int64_t>(i) * ldp + min(lane + kWave * c, npiv - 1)];
+      }
+#pragma unroll
+      for (int b = 0; b < kRows; ++b) {
+        double sum = 0.0;
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) sum = fma(v[b][c], yv[c], sum);
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) sum += __shfl_xor(sum, off, kWave);
+        const int i = wave + kSweepWaves * (r0 + b);
+        if (lane == 0 && i < npiv) dir_out[i] = ok ? static_cast<TO>(sum) : TO(0);
+      }
+    }
+  }
   if (threadIdx.x == 0 && status) *status = ok ? GNMPPI_OK : fail_code;
 }
 
 template <int R, typename TO>
 __global__ void __launch_bounds__(kSweepTD * kSweepTD) sweep_kernel(
     const double* __restrict__ M, int P, int npiv, int mode, TO* __restrict__ inv_out, int64_t ldo,
-    TO* __restrict__ dir_out, int32_t* status, int fail_code) {
-  sweep_matrix<R, TO>(M, P, npiv, mode, inv_out, ldo, dir_out, status, fail_code);
+    TO* __restrict__ dir_out, int32_t* status, int fail_code, const double* __restrict__ post,
+    int64_t ldp) {
+  sweep_matrix<R, TO>(M, P, npiv, mode, inv_out, ldo, dir_out, status, fail_code, post, ldp);
 }
 
-// Batched: MODE 0 inverts Gsum into Ginv (status word 0), MODE 1 solves the
-// GGN direction from Hsum into dU (status word 1).  One item per instance.
+// Batched: MODE 0 inverts Gsum into Ginv (status word 0: the rank check of
+// G), MODE 1 solves (S^T S + lambda G^2) y = -S^T r0 from Hsum and writes the
+// GGN direction dU = G y (status word 1).  One item per instance.
 template <int R, int MODE>
 __global__ void __launch_bounds__(kSweepTD * kSweepTD) batch_sweep_kernel(
     const BatchInst* __restrict__ inst, BatchLaunch L) {
@@ -524,10 +577,10 @@ __global__ void __launch_bounds__(kSweepTD * kSweepTD) batch_sweep_kernel(
     const BatchInst& b = inst[L.items[w].inst];
     if constexpr (MODE == 0)
       sweep_matrix<R, float>(b.Gsum, b.n, b.n, kSweepInverse, b.Ginv, b.npad, nullptr, b.status,
-                             GNMPPI_ERANK);
+                             GNMPPI_ERANK, nullptr, 0);
     else
       sweep_matrix<R, float>(b.Hsum, b.n + 1, b.n, kSweepDirection, nullptr, 0, b.dU,
-                             b.status + 1, GNMPPI_ENOTPD);
+                             b.status + 1, GNMPPI_ENOTPD, b.Gsum, b.n);
     __syncthreads();
   }
 }

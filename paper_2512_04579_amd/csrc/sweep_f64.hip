@@ -5,12 +5,13 @@
 namespace gnm {
 
 hipError_t launch_sweep(int P, int npiv, int mode, const double* M, double* inv_out, int64_t ldo,
-                        double* dir_out, int32_t* status, int fail_code, hipStream_t st) {
+                        double* dir_out, int32_t* status, int fail_code, hipStream_t st,
+                        const double* post, int64_t ldp) {
   const int R = (P + kSweepTD - 1) / kSweepTD;
-#define GNM_SWEEP_CASE(RR)                                                                       \
-  case RR:                                                                                       \
+#define GNM_SWEEP_CASE(RR)                                                                        \
+  case RR:                                                                                        \
     hipLaunchKernelGGL((sweep_kernel<RR, double>), dim3(1), dim3(kSweepTD * kSweepTD), 0, st, M, P, \
-                       npiv, mode, inv_out, ldo, dir_out, status, fail_code);                    \
+                       npiv, mode, inv_out, ldo, dir_out, status, fail_code, post, ldp);          \
     break;
   switch (R) {
     GNM_SWEEP_CASE(1) GNM_SWEEP_CASE(2) GNM_SWEEP_CASE(3) GNM_SWEEP_CASE(4) GNM_SWEEP_CASE(5)

@@ -70,11 +70,19 @@ class GNMPPI:
     Philox normals) or "sigma_points" (Method E, the 2n-point Dirac mixture)."""
 
     def __init__(self, dprob: DeviceProblem, x0, settings, seed: int = 1, U0=None,
-                 sampler: str = "gaussian", max_iters: int | None = None, overlap=False):
+                 sampler: str = "gaussian", max_iters: int | None = None, overlap=False,
+                 form_jacobian: bool = False):
         self.p = dprob
+        # form_jacobian: GetJacobian then the GGN step as two calls
+        # (gnmppi_reconstruct_jacobian, gnmppi_ggn_step), J formed in HBM;
+        # otherwise one gnmppi_ggn_direction call computes the same direction
+        # from S = dR W^T without forming J = S G^{-1}, with G = W W^T from
+        # the same contraction as S, on one stream (overlap is then unused).
+        self.form_jacobian = bool(form_jacobian)
         # G = W W^T and its inverse depend only on W, and W only on the seed
         # and the iteration, so (LS estimator only) they can be factored on a
-        # side stream that the main stream joins just before J = S G^{-1}.
+        # side stream that the main stream joins just before the first use
+        # of G (J = S G^{-1}, or the direction's normal matrix).
         # overlap = "ahead" (or True): the side stream draws its own copy of
         # the next iteration's W and factors its G into a second workspace
         # while the main stream finishes the current iteration and rolls out
@@ -92,7 +100,7 @@ class GNMPPI:
             raise ValueError("overlap must be False, True, 'ahead', 'prefetch' or 'same', "
                              f"not {overlap!r}")
         mode = "ahead" if overlap is True else overlap
-        self.overlap = bool(mode) and settings.jacobian == "ls"
+        self.overlap = bool(mode) and settings.jacobian == "ls" and self.form_jacobian
         self.ahead = self.overlap and mode in ("ahead", "prefetch")
         self.prefetch = self.overlap and mode == "prefetch"
         self.side = torch.cuda.Stream(device=dprob.device) if self.overlap else None
@@ -111,7 +119,7 @@ class GNMPPI:
         self.C = torch.zeros(K, dtype=dt, device=dev)
         self.r0 = torch.zeros(m, dtype=dt, device=dev)
         self.c0 = torch.zeros(1, dtype=dt, device=dev)
-        self.J = torch.zeros(m, n, dtype=dt, device=dev)
+        self.J = torch.zeros(m, n, dtype=dt, device=dev) if self.form_jacobian else None
         self.dU = torch.zeros(n, dtype=dt, device=dev)
         self.alpha = torch.tensor([settings.gamma ** j for j in range(settings.n_alpha)],
                                   dtype=dt, device=dev)
@@ -119,19 +127,25 @@ class GNMPPI:
         iters = max_iters if max_iters is not None else settings.iters
         self.info = torch.zeros(max(iters, 1), 3, dtype=torch.float64, device=dev)
         # status words per iteration: Jacobian (rank of G), GGN step (positive
-        # definiteness), G^{-1} factored on the side stream, line search (a
-        # finite candidate)
+        # definiteness; without J formed also the only check of G: a singular
+        # G makes S^T S singular), G^{-1} factored on the side stream, line
+        # search (a finite candidate); words that a path does not use stay 0
         self.status = torch.zeros(iters if iters else 1, 4, dtype=torch.int32, device=dev)
         code = _lib.F32 if dt == torch.float32 else _lib.F64
-        self.work_j = _workspace(_lib.gnmppi_jacobian_workspace(code, m, n, K), dev)
+        # the direction call's workspace is the Jacobian workspace followed by
+        # the GGN workspace
+        wbytes = (_lib.gnmppi_jacobian_workspace(code, m, n, K) if self.form_jacobian
+                  else _lib.gnmppi_ggn_direction_workspace(code, m, n, K))
+        self.work_j = _workspace(wbytes, dev)
         self.works = [self.work_j]
         self.W_side = None
         if self.ahead:
             # iteration it uses works[it % 2]; the side stream fills the other
-            self.works.append(_workspace(_lib.gnmppi_jacobian_workspace(code, m, n, K), dev))
+            self.works.append(_workspace(wbytes, dev))
             self.W_side = torch.zeros_like(self.W)
         self._gram_for = None  # iteration whose G^{-1} the side stream has been given
-        self.work_g = _workspace(_lib.gnmppi_ggn_workspace(code, m, n), dev)
+        self.work_g = (_workspace(_lib.gnmppi_ggn_workspace(code, m, n), dev) if self.form_jacobian
+                       else None)
         self.method = _lib.JAC_LS if settings.jacobian == "ls" else _lib.JAC_MC
         if dt == torch.float32:
             self.method |= {"native": 0, "bf16x3": _lib.JAC_BF16X3,
@@ -202,8 +216,11 @@ class GNMPPI:
             self.side.wait_event(sampled)
             with torch.cuda.stream(self.side):
                 _lib.gnmppi_perturbation_gram(W, work, self.m, self.status[it, 2:3], K)
-        tick.next("jacobian")
-        if self.overlap:
+        tick.next("jacobian" if self.form_jacobian else "direction")
+        j_done = None
+        if not self.form_jacobian:
+            self._direction(it, W, work, sig)
+        elif self.overlap:
             # S = dR W^T needs only the rollout; the join with the side stream
             # comes just before J = S G^{-1}
             method = self.method | _lib.JAC_GRAM_READY
@@ -214,7 +231,6 @@ class GNMPPI:
             _lib.gnmppi_reconstruct_jacobian(self.R[:, :K], self.r0, W, self.J, work,
                                              method | _lib.JAC_APPLY_ONLY, sig * sig,
                                              self.status[it, 0:1], K)
-            j_done = None
             if self.ahead:
                 if ahead and it + 1 < self.status.shape[0]:
                     # the next iteration's side work waits only for this J; it
@@ -227,15 +243,23 @@ class GNMPPI:
         else:
             _lib.gnmppi_reconstruct_jacobian(self.R[:, :K], self.r0, W, self.J, self.work_j,
                                              self.method, sig * sig, self.status[it, 0:1], K)
-        tick.next("ggn_step")
-        _lib.gnmppi_ggn_step(self.J, self.r0, self.s.lm_lambda, self.dU, self.work_g,
-                             self.status[it, 1:2])
+        if self.form_jacobian:
+            tick.next("ggn_step")
+            _lib.gnmppi_ggn_step(self.J, self.r0, self.s.lm_lambda, self.dU, self.work_g,
+                                 self.status[it, 1:2])
         tick.next("line_search")
         _lib.gnmppi_line_search(self.p, self.x0, self.U, self.dU, self.alpha, self.C_line,
                                 self.info[it], self.status[it, 3:4])
         tick.stop()
         if self.overlap and j_done is not None:
             self._side_gram(it + 1, after=j_done)
+
+    def _direction(self, it: int, W, work, sig: float):
+        """GetJacobian and the GGN step of iteration ``it`` as one
+        gnmppi_ggn_direction call (J is not formed; for LS, G = W W^T comes
+        out of the same contraction as S)."""
+        _lib.gnmppi_ggn_direction(self.R[:, :self.K], self.r0, W, self.dU, work, self.method,
+                                  sig * sig, self.s.lm_lambda, self.status[it, 1:2], K=self.K)
 
     def capture(self, iters: int, it0: int = 0):
         """Captures iterations it0 .. it0 + iters - 1 into one HIP graph.
@@ -279,6 +303,20 @@ class GNMPPI:
     def history(self, iters: int):
         info = self.info[:iters].cpu()
         return info[:, 1].double().numpy(), info[:, 0].double().numpy(), self.status[:iters].cpu().numpy()
+
+
+# Iteration schedules of GNMPPI: "direct" -- one gnmppi_ggn_direction call per
+# iteration (J not formed), one stream; "formed" -- J formed
+# (gnmppi_reconstruct_jacobian, then gnmppi_ggn_step), one stream; "ahead",
+# "prefetch", "same" -- J formed, with G^{-1} factored on a side stream.
+SCHEDULES = {"direct": (False, False), "formed": (True, False), "ahead": (True, "ahead"),
+             "prefetch": (True, "prefetch"), "same": (True, "same")}
+
+
+def make_solver(dprob: DeviceProblem, x0, settings, schedule: str = "direct", **kw) -> GNMPPI:
+    """GNMPPI with the iteration schedule ``schedule`` (a key of SCHEDULES)."""
+    form, overlap = SCHEDULES[schedule]
+    return GNMPPI(dprob, x0, settings, overlap=overlap, form_jacobian=form, **kw)
 
 
 class PlainMPPI:

@@ -192,7 +192,7 @@ def solve_pairs(workload, X0: np.ndarray, iters: int, seed: int | None = None, l
     p, st = workload.problem, workload.settings
     dp = DeviceProblem(p, workload.dtype)
     solver = GNMPPI(dp, workload.x0, st, seed=workload.noise_seed if seed is None else seed,
-                    max_iters=iters, overlap=True)
+                    max_iters=iters)
     graph = solver.capture(iters)
     count = X0.shape[0]
     Xd = torch.tensor(X0, dtype=solver.x0.dtype, device=dp.device)

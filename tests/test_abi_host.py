@@ -151,7 +151,7 @@ def test_other_entry_points_reject_bad_arguments():
 def test_status_strings_and_version():
     assert _lib.status_string(_lib.ENOTPD) == "normal matrix not positive definite"
     assert _lib.status_string(123) == "unknown status"
-    assert _lib.gnmppi_abi_version() == 2
+    assert _lib.gnmppi_abi_version() == 3
 
 
 def test_mlp_entry_points_reject_bad_arguments():
@@ -168,6 +168,34 @@ def test_mlp_entry_points_reject_bad_arguments():
                                    None) == _lib.EINVAL
     assert lib.gnmppi_mlp_adam(10, 0x10, 0x20, 0x30, 0x40, 0x50, 1e-3, 0.9, 0.999, 1e-8, 0, None) == _lib.EINVAL
     assert lib.gnmppi_mlp_adam(10, 0x10, 0x20, 0x30, 0x40, 0x50, 1e-3, 1.0, 0.999, 1e-8, 1, None) == _lib.EINVAL
+
+
+def test_ggn_direction_rejects_bad_arguments():
+    lib = _lib.load()
+    LS_READY = _lib.JAC_LS | _lib.JAC_GRAM_READY
+    ws = lib.gnmppi_ggn_direction_workspace(_lib.F32, 3300, 100, 4096)
+    # the Jacobian workspace followed by the GGN workspace
+    assert ws == lib.gnmppi_jacobian_workspace(_lib.F32, 3300, 100, 4096) + \
+        lib.gnmppi_ggn_workspace(_lib.F32, 3300, 100)
+    assert lib.gnmppi_ggn_direction_workspace(_lib.F32, 0, 100, 4096) == 0
+
+    def call(method, dtype=_lib.F32, n=100, sigma2=0.1, lam=0.0, work=0x1000, wbytes=ws, ldr=4096):
+        return lib.gnmppi_ggn_direction(dtype, 3300, n, 4096, 0x100, ldr, 0x200, 0x300, 4096, method,
+                                        sigma2, lam, 0x400, work, wbytes, None, None)
+
+    for method in (_lib.JAC_MC | _lib.JAC_GRAM_READY, _lib.JAC_MC | _lib.JAC_S_ONLY,
+                   LS_READY | _lib.JAC_S_ONLY | _lib.JAC_APPLY_ONLY,
+                   LS_READY | _lib.JAC_BF16 | _lib.JAC_BF16X3, LS_READY | 0x2000, 2):
+        assert call(method) == _lib.EINVAL
+    assert call(_lib.JAC_MC, sigma2=0.0) == _lib.EINVAL
+    assert call(LS_READY, lam=-1.0) == _lib.EINVAL
+    assert call(LS_READY, lam=float("inf")) == _lib.EINVAL
+    assert call(LS_READY, n=193) == _lib.EINVAL
+    assert call(LS_READY, ldr=4095) == _lib.EINVAL
+    assert call(LS_READY, work=0x1008) == _lib.EINVAL
+    assert call(LS_READY, wbytes=ws - 1) == _lib.ENOSPACE
+    wsd = lib.gnmppi_ggn_direction_workspace(_lib.F64, 3300, 100, 4096)
+    assert call(LS_READY | _lib.JAC_BF16X3, dtype=_lib.F64, wbytes=wsd) == _lib.EINVAL
 
 
 def test_noalloc_ggn_step_rejects_without_touching_a_device():

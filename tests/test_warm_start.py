@@ -53,7 +53,7 @@ def test_warm_start_beats_the_zero_start():
 
     dp = DeviceProblem(p, "f32")
     iters = 2
-    solver = GNMPPI(dp, w.x0, w.settings, seed=w.noise_seed + 50, max_iters=iters, overlap=True)
+    solver = GNMPPI(dp, w.x0, w.settings, seed=w.noise_seed + 50, max_iters=iters)
     graph = solver.capture(iters)
     zero_starts, warm_starts, chosen = [], [], []
     for x0 in X_test:
