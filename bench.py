@@ -56,6 +56,9 @@ def algorithmic_work(prob, K: int, L: int, esize: int):
     fss = flops_per_sample_step(prob)
     return {
         "rollout": {"bytes": (K + 1) * m * esize + K * n * esize, "flops": (K + 1) * N * fss},
+        # the same launch drawing W itself: W written instead of read
+        "sample_rollout": {"bytes": (K + 1) * m * esize + K * n * esize,
+                           "flops": (K + 1) * N * fss},
         "jacobian": {"bytes": m * K * esize + n * K * esize + m * n * esize,
                      "flops": 2.0 * m * n * K + 2.0 * n * n * K + 2.0 * m * n * n},
         "ggn_step": {"bytes": m * n * esize + m * esize, "flops": 2.0 * m * (n + 1) ** 2 + n ** 3 / 3.0},
@@ -83,7 +86,8 @@ def rollout_traffic(name: str, esize: int):
             kv[k.strip()] = v.strip()
     import hashlib
     h = hashlib.sha256()
-    for f in ("paper_2512_04579_amd/csrc/rollout.hip", "paper_2512_04579_amd/csrc/common.hpp"):
+    for f in ("paper_2512_04579_amd/csrc/rollout.hip", "paper_2512_04579_amd/csrc/common.hpp",
+              "paper_2512_04579_amd/csrc/philox.hpp"):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     if kv.get("kernel_source_sha256") != h.hexdigest():
@@ -462,14 +466,20 @@ def bench_single(w, args, steps_req: int, warmup: int):
         solver.step(it, marks)
         torch.cuda.synchronize()
     per_call_us = {k: 1e3 * float(np.median([a.elapsed_time(b) for a, b in v])) for k, v in marks.items()}
+    # the launch that the iteration runs: W drawn inside the rollout
     Kc = solver.K
     Wv, Rv = solver.W[:, :Kc], solver.R[:, :Kc]
+
+    def rollout_launch():
+        _lib.gnmppi_sample_rollout(dp, solver.x0, solver.U, Wv, solver.sigma(0), solver.seed, 0, Kc,
+                                   antithetic=st.antithetic, R=Rv, r0=solver.r0, c0=solver.c0)
+
     for _ in range(3):
-        _lib.gnmppi_rollout(dp, solver.x0, solver.U, Wv, Kc, Rv, None, solver.r0, solver.c0)
+        rollout_launch()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(args.kernel_reps):
-        _lib.gnmppi_rollout(dp, solver.x0, solver.U, Wv, Kc, Rv, None, solver.r0, solver.c0)
+        rollout_launch()
     e1.record()
     torch.cuda.synchronize()
     rollout_us = e0.elapsed_time(e1) * 1e3 / args.kernel_reps

@@ -161,6 +161,21 @@ int gnmppi_rollout(const gnmppi_problem *p, const void *x0, const void *U,
                    void *R, int64_t ldr, void *C,
                    void *r0, void *c0, void *stream);
 
+/* ---- a1 + a2 in one launch ----------------------------------------------
+ * gnmppi_sample(dtype, n = N nu, K, sigma, seed, stream_id, antithetic, W,
+ * ldw) followed by gnmppi_rollout(p, x0, U, W, ldw, K, R, ldr, C, r0, c0),
+ * with the same results bit for bit: W (written, not read) holds the draws
+ * and R, C, r0, c0 the rollout of U + W[:, s].  For the chain model with
+ * staged controls and residuals wanted (R or r0 non-NULL) each rollout block
+ * draws its own columns of W while it stages its controls, so the sampler
+ * is not a launch of its own; otherwise the two run one after the other.
+ * Errors: those of both calls (K >= 1 here). */
+int gnmppi_sample_rollout(const gnmppi_problem *p, const void *x0, const void *U,
+                          double sigma, uint64_t seed, uint64_t stream_id,
+                          int32_t antithetic, void *W, int64_t ldw, int32_t K,
+                          void *R, int64_t ldr, void *C, void *r0, void *c0,
+                          void *stream);
+
 /* ---- a3: MPPI update (Eqs. (7), (8)) ------------------------------------
  * U <- U + sum_s w_s W[:, s] / sum_s w_s with w_s = exp(-(C_s - min C)/temperature).
  * The shift by min C cancels in the ratio.  Samples with a NaN or infinite

@@ -74,6 +74,9 @@ SIGNATURES = {
     "gnmppi_sigma_points": (c_int32, [c_int32, c_int32, c_double, c_void_p, c_int64, c_void_p]),
     "gnmppi_rollout": (c_int32, [PROBLEM_P, c_void_p, c_void_p, c_void_p, c_int64, c_int32,
                                  c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "gnmppi_sample_rollout": (c_int32, [PROBLEM_P, c_void_p, c_void_p, c_double, c_uint64, c_uint64,
+                                        c_int32, c_void_p, c_int64, c_int32, c_void_p, c_int64,
+                                        c_void_p, c_void_p, c_void_p, c_void_p]),
     "gnmppi_mppi_update": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_int64,
                                      c_double, c_void_p, c_void_p, c_void_p, c_void_p]),
     "gnmppi_jacobian_workspace": (c_size_t, [c_int32, c_int32, c_int32, c_int32]),
@@ -200,6 +203,15 @@ def gnmppi_rollout(problem, x0, U, W, K: int, R=None, C=None, r0=None, c0=None, 
     _check("gnmppi_rollout", load().gnmppi_rollout(
         ctypes.byref(problem.c), _ptr(x0), _ptr(U), _ptr(W), _ld(W), int(K), _ptr(R), _ld(R),
         _ptr(C), _ptr(r0), _ptr(c0), _stream(stream)))
+
+
+def gnmppi_sample_rollout(problem, x0, U, W, sigma: float, seed: int, stream_id: int, K: int,
+                          antithetic: bool = True, R=None, C=None, r0=None, c0=None, stream=None):
+    """gnmppi_sample into ``W`` and gnmppi_rollout of U + W in one call."""
+    _check("gnmppi_sample_rollout", load().gnmppi_sample_rollout(
+        ctypes.byref(problem.c), _ptr(x0), _ptr(U), float(sigma), int(seed) & (2 ** 64 - 1),
+        int(stream_id) & (2 ** 64 - 1), 1 if antithetic else 0, _ptr(W), _ld(W), int(K), _ptr(R), _ld(R), _ptr(C), _ptr(r0),
+        _ptr(c0), _stream(stream)))
 
 
 def gnmppi_mppi_update(C, W, temperature: float, U, weights=None, status=None, K: int | None = None,

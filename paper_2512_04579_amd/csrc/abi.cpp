@@ -78,6 +78,23 @@ int gnmppi_rollout(const gnmppi_problem* p, const void* x0, const void* U, const
                                        as_stream(stream)));
 }
 
+int gnmppi_sample_rollout(const gnmppi_problem* p, const void* x0, const void* U, double sigma,
+                          uint64_t seed, uint64_t stream_id, int32_t antithetic, void* W,
+                          int64_t ldw, int32_t K, void* R, int64_t ldr, void* C, void* r0,
+                          void* c0, void* stream) {
+  if (!problem_ok(p) || !sizes_fit(p) || x0 == nullptr || U == nullptr || W == nullptr)
+    return GNMPPI_EINVAL;
+  if (K < 1 || ldw < K || (antithetic && (K % 2) != 0) || !std::isfinite(sigma))
+    return GNMPPI_EINVAL;
+  if (static_cast<int64_t>(p->N) * p->nu > 65535 * 2) return GNMPPI_EINVAL;
+  if (C == nullptr && R == nullptr) return GNMPPI_EINVAL;
+  if (R != nullptr && ldr < K) return GNMPPI_EINVAL;
+  if (r0 != nullptr && c0 == nullptr) return GNMPPI_EINVAL;
+  if (static_cast<int64_t>(K) * 16 >= (int64_t{1} << 31)) return GNMPPI_EINVAL;
+  return status_of(gnm::launch_sample_rollout(*p, x0, U, sigma, seed, stream_id, antithetic != 0,
+                                              W, ldw, K, R, ldr, C, r0, c0, as_stream(stream)));
+}
+
 int gnmppi_mppi_update(int32_t dtype, int32_t n, int32_t K, const void* C, const void* W,
                        int64_t ldw, double temperature, void* U, void* weights, int32_t* status,
                        void* stream) {

@@ -19,6 +19,12 @@ hipError_t launch_sigma_points(int dtype, int n, double sigma, void* W, int64_t 
 hipError_t launch_rollout(const gnmppi_problem& p, const void* x0, const void* U,
                           const void* W, int64_t ldw, int K, void* R, int64_t ldr,
                           void* C, void* r0, void* c0, hipStream_t st);
+// Sampler and rollout in one launch where the chain's split kernel runs (else
+// the sampler, then the rollout): W is written, not read.
+hipError_t launch_sample_rollout(const gnmppi_problem& p, const void* x0, const void* U,
+                                 double sigma, uint64_t seed, uint64_t stream_id, int antithetic,
+                                 void* W, int64_t ldw, int K, void* R, int64_t ldr, void* C,
+                                 void* r0, void* c0, hipStream_t st);
 hipError_t launch_line_search(const gnmppi_problem& p, const void* x0, void* U,
                               const void* dU, const void* alpha, int L, void* C,
                               double* info, int32_t* status, hipStream_t st);

@@ -17,6 +17,7 @@
 #include "batch.hpp"
 #include "common.hpp"
 #include "launch.hpp"
+#include "philox.hpp"
 
 namespace gnm {
 namespace {
@@ -457,12 +458,25 @@ constexpr int split_flush_steps() {
 // one rollout wave per SIMD a store that waits for the memory queue would
 // hold up the RK4 steps of its SIMD; here it holds only a storing wave.
 // Controls are staged in LDS (dynamic shared memory).
+// Perturbations drawn by the rollout itself (Wout != nullptr): the draws of
+// the sampler (gnmppi_sample with this key and stream, antithetic pairs when
+// Kdraw < K), written to Wout for the later contraction while the block
+// stages its controls U + W[:, s].
+template <typename T>
+struct RolloutDraw {
+  T* Wout;
+  T sigma;
+  uint32_t k0, k1, s0, s1;
+  int Kdraw;
+};
+
 template <typename T, int G, int F>
 __global__ void __launch_bounds__(2 * kBlock) rollout_chain_split_kernel(
     ChainDev<T> cd, int N, const T* __restrict__ x0, const T* __restrict__ q,
     const T* __restrict__ r, const T* __restrict__ xref, const T* __restrict__ U,
     const T* __restrict__ W, int64_t ldw, int K, T* __restrict__ R, int64_t ldr,
-    T* __restrict__ C, T* __restrict__ r0, T* __restrict__ c0, int nblocks) {
+    T* __restrict__ C, T* __restrict__ r0, T* __restrict__ c0, int nblocks,
+    RolloutDraw<T> draw) {
   using Tile = ResidualTile<T, G, F>;
   constexpr int kSpb = Tile::kSpb;
   __shared__ T tile[2][F * Tile::kRows][Tile::kLd];
@@ -472,11 +486,34 @@ __global__ void __launch_bounds__(2 * kBlock) rollout_chain_split_kernel(
   const int col0 = g * kSpb;
   const int n = 2 * N;
   T* ctl = reinterpret_cast<T*>(ctl_raw);
-  for (int e = threadIdx.x; e < n * kSpb; e += 2 * kBlock) {
-    const int idx = e / kSpb, sl = e % kSpb, c = col0 + sl;
-    T u = U[idx];
-    if (W != nullptr && c < K) u += W[idx * ldw + c];
-    ctl[e] = u;
+  if (draw.Wout != nullptr) {
+    // one Philox block (philox_rows<T>() rows) of one column per item
+    constexpr int kr = philox_rows<T>();
+    for (int e = threadIdx.x; e < (n + kr - 1) / kr * kSpb; e += 2 * kBlock) {
+      const int b = e / kSpb, sl = e % kSpb, c = col0 + sl;
+      const bool drawn = c < K;
+      const bool mirror = c >= draw.Kdraw;  // antithetic partner of column c - Kdraw
+      T v[kr];
+      scaled_normals<T>(static_cast<uint32_t>(mirror ? c - draw.Kdraw : c),
+                        static_cast<uint32_t>(b), draw.k0, draw.k1, draw.s0, draw.s1,
+                        draw.sigma, v);
+#pragma unroll
+      for (int t = 0; t < kr; ++t) {
+        const int row = kr * b + t;
+        if (row < n) {
+          const T w = mirror ? -v[t] : v[t];
+          if (drawn) draw.Wout[row * ldw + c] = w;
+          ctl[row * kSpb + sl] = drawn ? U[row] + w : U[row];
+        }
+      }
+    }
+  } else {
+    for (int e = threadIdx.x; e < n * kSpb; e += 2 * kBlock) {
+      const int idx = e / kSpb, sl = e % kSpb, c = col0 + sl;
+      T u = U[idx];
+      if (W != nullptr && c < K) u += W[idx * ldw + c];
+      ctl[e] = u;
+    }
   }
   __syncthreads();
   const bool has_nominal = c0 != nullptr && col0 <= K && K < col0 + kSpb;  // uniform
@@ -741,10 +778,13 @@ ChainDev<T> chain_dev(const gnmppi_problem& p) {
                      static_cast<T>(p.k_cub), static_cast<T>(1.0 / p.mass)};
 }
 
+// With draw.Wout != nullptr (and W == nullptr) the perturbations are drawn
+// in the same launch when the split kernel runs (staged controls, residuals
+// wanted); otherwise the sampler runs first and the rollout reads its W.
 template <typename T>
 hipError_t rollout_typed(const gnmppi_problem& p, const T* x0, const T* U, const T* W,
                          int64_t ldw, int K, T* R, int64_t ldr, T* C, T* r0, T* c0,
-                         hipStream_t st) {
+                         hipStream_t st, RolloutDraw<T> draw = RolloutDraw<T>{}) {
   const T* q = static_cast<const T*>(p.q);
   const T* r = static_cast<const T*>(p.r);
   const T* xr = static_cast<const T*>(p.x_ref);
@@ -760,12 +800,22 @@ hipError_t rollout_typed(const gnmppi_problem& p, const T* x0, const T* U, const
     // residuals with staged controls: the split kernel (rollout and storing
     // waves); costs only: the plain one
     const bool split = stage && (R != nullptr || r0 != nullptr);
+    if (draw.Wout != nullptr && !split) {
+      const uint64_t seed = (static_cast<uint64_t>(draw.k1) << 32) | draw.k0;
+      const uint64_t sid = (static_cast<uint64_t>(draw.s1) << 32) | draw.s0;
+      const hipError_t e = launch_sample(sizeof(T) == 4 ? GNMPPI_F32 : GNMPPI_F64, p.N * p.nu, K,
+                                         static_cast<double>(draw.sigma), seed, sid,
+                                         draw.Kdraw < K, draw.Wout, ldw, st);
+      if (e != hipSuccess) return e;
+      W = draw.Wout;
+      draw.Wout = nullptr;
+    }
 #define GNM_CHAIN_CASE(GG)                                                                      \
   case GG:                                                                                      \
     if (split)                                                                                  \
       hipLaunchKernelGGL((rollout_chain_split_kernel<T, GG, split_flush_steps<T, GG>()>), grid, \
                          dim3(2 * kBlock), lds, st, cd, p.N, x0, q, r, xr, U, W, ldw, K, R, ldr, \
-                         C, r0, c0, nblocks);                                                   \
+                         C, r0, c0, nblocks, draw);                                             \
     else                                                                                        \
       hipLaunchKernelGGL((rollout_chain_kernel<T, GG>), grid, dim3(kBlock), lds, st, cd, p.N,   \
                          x0, q, r, xr, U, W, ldw, K, R, ldr, C, r0, c0, nblocks, stage);        \
@@ -864,6 +914,36 @@ hipError_t launch_rollout(const gnmppi_problem& p, const void* x0, const void* U
                                static_cast<const double*>(W), ldw, K, static_cast<double*>(R),
                                ldr, static_cast<double*>(C), static_cast<double*>(r0),
                                static_cast<double*>(c0), st);
+}
+
+hipError_t launch_sample_rollout(const gnmppi_problem& p, const void* x0, const void* U,
+                                 double sigma, uint64_t seed, uint64_t stream_id, int antithetic,
+                                 void* W, int64_t ldw, int K, void* R, int64_t ldr, void* C,
+                                 void* r0, void* c0, hipStream_t st) {
+  const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
+  const uint32_t s0 = static_cast<uint32_t>(stream_id), s1 = static_cast<uint32_t>(stream_id >> 32);
+  const int Kdraw = antithetic ? K / 2 : K;
+  if (p.model != GNMPPI_MODEL_CHAIN) {
+    // the one-lane-per-sample kernel reads W: sampler, then rollout
+    const hipError_t e = launch_sample(p.dtype, p.N * p.nu, K, sigma, seed, stream_id, antithetic,
+                                       W, ldw, st);
+    if (e != hipSuccess) return e;
+    return launch_rollout(p, x0, U, W, ldw, K, R, ldr, C, r0, c0, st);
+  }
+  if (p.dtype == GNMPPI_F32)
+    return rollout_typed<float>(p, static_cast<const float*>(x0), static_cast<const float*>(U),
+                                nullptr, ldw, K, static_cast<float*>(R), ldr,
+                                static_cast<float*>(C), static_cast<float*>(r0),
+                                static_cast<float*>(c0), st,
+                                RolloutDraw<float>{static_cast<float*>(W),
+                                                   static_cast<float>(sigma), k0, k1, s0, s1,
+                                                   Kdraw});
+  return rollout_typed<double>(p, static_cast<const double*>(x0), static_cast<const double*>(U),
+                               nullptr, ldw, K, static_cast<double*>(R), ldr,
+                               static_cast<double*>(C), static_cast<double*>(r0),
+                               static_cast<double*>(c0), st,
+                               RolloutDraw<double>{static_cast<double*>(W), sigma, k0, k1, s0, s1,
+                                                   Kdraw});
 }
 
 int batch_chain_group(int M) { return chain_group(M); }

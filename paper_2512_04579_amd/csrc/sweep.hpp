@@ -499,6 +499,7 @@ __device__ __forceinline__ void sweep_matrix(
   __shared__ double wmax[kSweepWaves];
   __shared__ int diag_ok[2];
   __shared__ double ydir[16 * R];
+  __shared__ double ypart[kSweepWaves * kWave > 16 * R ? kSweepWaves * kWave : 16 * R];
   const SweepLds L{pan,           ybufw,          ybufp,    tiles16,  tiles16 + 2 * TL,
                    tiles16 + 4 * TL, tiles16 + 6 * TL, wmax, diag_ok, 16 * R * LD};
   const int lane = threadIdx.x & (kWave - 1);
@@ -520,40 +521,43 @@ __device__ __forceinline__ void sweep_matrix(
     ok = sweep_update_role<R, 3, TO>(L, M, P, npiv, solve_only, lane, inv, ldo, dir_out, yd);
   if (postmul) {
     __syncthreads();
-    // dir_out[i] = sum_j post[i][j] y_j: wave w takes rows w, w + 4, ...,
-    // lane l columns l, l + 64, ...; the loads of kRows rows are issued
-    // together (one memory round trip per batch of rows, not per row) and
-    // each row's products are summed over the wave by a fixed butterfly
-    constexpr int kChunks = (16 * R + kWave - 1) / kWave;
-    constexpr int kRowsPerWave = (16 * R + kSweepWaves - 1) / kSweepWaves;
-    constexpr int kRowsMax = kChunks >= 4 ? 8 : 32 / kChunks;
-    constexpr int kRows = kRowsMax < kRowsPerWave ? kRowsMax : kRowsPerWave;
-    double yv[kChunks];
-#pragma unroll
-    for (int c = 0; c < kChunks; ++c) {
-      const int j = lane + kWave * c;
-      yv[c] = j < npiv ? ydir[j] : 0.0;
-    }
+    // dir_out[i] = sum_j post[j][i] y_j (post is symmetric): thread t owns
+    // output i = t % kOut for the columns j = h, h + kGroups, ... with
+    // h = t / kOut, so each j is one contiguous row segment across the
+    // threads; kBatch loads per thread are issued before their products (one
+    // memory round trip per batch), and the kGroups partial sums of an output
+    // are added in group order through LDS
+    constexpr int kOut = 16 * R;
+    constexpr int kGroups = (kSweepWaves * kWave) / kOut > 0 ? (kSweepWaves * kWave) / kOut : 1;
+    constexpr int kPerThread = (kOut + kGroups - 1) / kGroups;
+    constexpr int kBatch = kPerThread < 32 ? kPerThread : 32;
+    const int t = threadIdx.x;
+    const int i = t % kOut, h = t / kOut;
+    double sum = 0.0;
+    if (h < kGroups) {
+      const int ic = min(i, npiv - 1);
 #pragma unroll 1
-    for (int r0 = 0; r0 < kRowsPerWave; r0 += kRows) {
-      double v[kRows][kChunks];
+      for (int q0 = 0; q0 < kPerThread; q0 += kBatch) {
+        double v[kBatch];
 #pragma unroll
-      for (int b = 0; b < kRows; ++b) {
-        const int i = min(wave + kSweepWaves * (r0 + b), npiv - 1);
+        for (int q = 0; q < kBatch; ++q) {
+          const int j = h + kGroups * (q0 + q);
+          v[q] = post[static_cast<int64_t>(min(j, npiv - 1)) * ldp + ic];
+        }
 #pragma unroll
-        for (int c = 0; c < kChunks; ++c)
-          v[b][c] = post[static_cast<int64_t>(i) * ldp + min(lane + kWave * c, npiv - 1)];
+        for (int q = 0; q < kBatch; ++q) {
+          const int j = h + kGroups * (q0 + q);
+          sum = fma(v[q], j < npiv ? ydir[j] : 0.0, sum);
+        }
       }
+      ypart[h * kOut + i] = sum;
+    }
+    __syncthreads();
+    if (t < npiv) {
+      double d = ypart[t];
 #pragma unroll
-      for (int b = 0; b < kRows; ++b) {
-        double sum = 0.0;
-#pragma unroll
-        for (int c = 0; c < kChunks; ++c) sum = fma(v[b][c], yv[c], sum);
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) sum += __shfl_xor(sum, off, kWave);
-        const int i = wave + kSweepWaves * (r0 + b);
-        if (lane == 0 && i < npiv) dir_out[i] = ok ? static_cast<TO>(sum) : TO(0);
-      }
+      for (int g = 1; g < kGroups; ++g) d += ypart[g * kOut + t];
+      dir_out[t] = ok ? static_cast<TO>(d) : TO(0);
     }
   }
   if (threadIdx.x == 0 && status) *status = ok ? GNMPPI_OK : fail_code;

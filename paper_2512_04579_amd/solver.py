@@ -196,26 +196,35 @@ class GNMPPI:
         if self.ahead and self._gram_for != it:
             self._side_gram(it)  # not enqueued by a preceding step
         tick = _Ticker(marks)
-        tick.start("sample")
-        if self.prefetch:
-            # W of this iteration comes from the side stream (its G^{-1} is
-            # joined before J as in "ahead")
-            torch.cuda.current_stream().wait_event(self._w_ready)
-            W = self.W_side[:, :K]
+        if not self.overlap and self.sampler == "gaussian":
+            # one launch draws W and rolls out (residuals and the nominal
+            # cost only: the step never reads C)
+            tick.start("sample_rollout")
+            _lib.gnmppi_sample_rollout(self.p, self.x0, self.U, W, self.sigma(it), self.seed, it, K,
+                                       antithetic=self.s.antithetic, R=self.R[:, :K], r0=self.r0,
+                                       c0=self.c0)
         else:
-            self._sample(W, it)
-        if self.overlap and not self.ahead:
-            sampled = torch.cuda.Event()
-            sampled.record()
-        tick.next("rollout")
-        # residuals and the nominal cost only: the step never reads C
-        _lib.gnmppi_rollout(self.p, self.x0, self.U, W, K, self.R[:, :K], None, self.r0, self.c0)
-        if self.overlap and not self.ahead:
-            # enqueued after the rollout so that a captured graph keeps the
-            # rollout on the sampling queue and forks only the W-only work
-            self.side.wait_event(sampled)
-            with torch.cuda.stream(self.side):
-                _lib.gnmppi_perturbation_gram(W, work, self.m, self.status[it, 2:3], K)
+            tick.start("sample")
+            if self.prefetch:
+                # W of this iteration comes from the side stream (its G^{-1} is
+                # joined before J as in "ahead")
+                torch.cuda.current_stream().wait_event(self._w_ready)
+                W = self.W_side[:, :K]
+            else:
+                self._sample(W, it)
+            if self.overlap and not self.ahead:
+                sampled = torch.cuda.Event()
+                sampled.record()
+            tick.next("rollout")
+            # residuals and the nominal cost only: the step never reads C
+            _lib.gnmppi_rollout(self.p, self.x0, self.U, W, K, self.R[:, :K], None, self.r0,
+                                self.c0)
+            if self.overlap and not self.ahead:
+                # enqueued after the rollout so that a captured graph keeps the
+                # rollout on the sampling queue and forks only the W-only work
+                self.side.wait_event(sampled)
+                with torch.cuda.stream(self.side):
+                    _lib.gnmppi_perturbation_gram(W, work, self.m, self.status[it, 2:3], K)
         tick.next("jacobian" if self.form_jacobian else "direction")
         j_done = None
         if not self.form_jacobian:

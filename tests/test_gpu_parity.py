@@ -191,6 +191,41 @@ def test_eager_steps_with_a_side_stream_match_one_stream(schedule):
     assert (two.history(3)[2] == 0).all()
 
 
+@pytest.mark.parametrize("name,outputs", [("c2", "R"), ("c1", "R"), ("chain3_f32_ragged", "R"),
+                                          ("chain5_f64_padding_lanes", "R"), ("chain1_f32", "R"),
+                                          ("chain16_f64", "R"), ("c2", "C"), ("c2", "RC")])
+def test_sample_rollout_equals_the_sampler_then_the_rollout(name, outputs):
+    # one launch that draws W itself (chain, residuals wanted) or the two
+    # calls in a row (double integrator, costs only): bit for bit the same W,
+    # R, r0, c0 and C as gnmppi_sample followed by gnmppi_rollout
+    prob, x0, dtype, K, anti = _rollout_case(name)
+    dp = DeviceProblem(prob, dtype)
+    rng = np.random.default_rng(zlib.crc32(name.encode()) + 1)
+    Ud = to_dev(rnd(0.2 * rng.standard_normal(prob.n), dtype), dtype)
+    x0d = to_dev(rnd(x0, dtype), dtype)
+    seed, sid, sigma = 0x5EED_0000_1234, 17, 0.3
+    outs = []
+    for fused in (False, True):
+        Wd = padded(np.full((prob.n, K), 9.0), dtype, ld=K + 3)
+        R = padded(np.zeros((prob.m, K)), dtype) if "R" in outputs else None
+        C = to_dev(np.zeros(K), dtype) if "C" in outputs else None
+        r0 = to_dev(np.zeros(prob.m), dtype) if "R" in outputs else None
+        c0 = to_dev(np.zeros(1), dtype)
+        if fused:
+            _lib.gnmppi_sample_rollout(dp, x0d, Ud, Wd, sigma, seed, sid, K, antithetic=anti, R=R,
+                                       C=C, r0=r0, c0=c0)
+        else:
+            _lib.gnmppi_sample(Wd, sigma, seed, sid, antithetic=anti, K=K)
+            _lib.gnmppi_rollout(dp, x0d, Ud, Wd, K, R, C, r0, c0)
+        _sync()
+        outs.append([host(t) for t in (Wd, R, C, r0, c0) if t is not None])
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(b, a)
+    ref = philox.perturbations(prob.n, K, sigma, seed=seed, stream=sid, dtype=dtype, antithetic=anti)
+    np.testing.assert_allclose(outs[1][0], ref, rtol=2e-6 if dtype == "f32" else 1e-13,
+                               atol=2e-6 if dtype == "f32" else 1e-13)
+
+
 def test_chain_rest_pose_is_a_fixed_point_on_device():
     prob, _ = wl.chain_problem(n_masses=16, N=50, seed=2)
     dp = DeviceProblem(prob, "f64")
