@@ -33,6 +33,15 @@ HIPCC_FLAGS = [
 ]
 
 
+# The sweep units keep their f64 MFMA accumulators in ordinary VGPRs: the
+# update waves select between tiles and zero pivot rows in place, which with
+# accumulators in AGPRs costs a copy out and back for every tile (measured: the
+# sweep 11 % faster, no spills).
+EXTRA_FLAGS = {src: ["-mllvm", "-amdgpu-mfma-vgpr-form"]
+               for src in ("sweep_batch_inv.hip", "sweep_batch_dir.hip", "sweep_f32.hip",
+                           "sweep_f64.hip")}
+
+
 def _hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc"):
         if cand and os.path.exists(cand):
@@ -43,8 +52,8 @@ def _hipcc() -> str:
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"] if src.endswith(".cpp") else []
-    cmd = [_hipcc(), *HIPCC_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", *lang, "-c",
-           os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc(), *HIPCC_FLAGS, *EXTRA_FLAGS.get(src, []), f"-I{INCLUDE}", f"-I{CSRC}", *lang,
+           "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

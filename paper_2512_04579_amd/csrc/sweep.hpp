@@ -279,8 +279,14 @@ struct SweepLds {
 };
 
 // Wave 0.  Tile (b, b) arrives in dtin[b & 1] with blocks < b - 1 applied.
+// In the last phase it has no pivots and waits for the update waves: it then
+// reads one word of every 128-byte line of `warm` (warm_bytes bytes, the
+// matrix of the post-multiplication), so that those lines are in this XCD's
+// L2 when the epilogue reads them; warm_acc keeps the words so the loads stay.
 template <int R>
-__device__ __forceinline__ bool sweep_pivot_role(const SweepLds& L, int npiv, int lane) {
+__device__ __forceinline__ bool sweep_pivot_role(const SweepLds& L, int npiv, int lane,
+                                                 const double* warm, int64_t warm_bytes,
+                                                 uint32_t& warm_acc) {
   constexpr int LD = kSweepLd, TL = 16 * LD;
   const int li = lane & 15, q = lane >> 4;
   const int nblk = (npiv + 15) / 16;
@@ -326,6 +332,20 @@ __device__ __forceinline__ bool sweep_pivot_role(const SweepLds& L, int npiv, in
         dt[k * LD + li] = d4[e];
       }
       if (lane == 0) L.diag_ok[b & 1] = okb;
+    } else if (warm != nullptr) {
+      const char* base = reinterpret_cast<const char*>(warm);
+      constexpr int kLines = 8;  // loads in flight per lane and round
+      for (int64_t o0 = static_cast<int64_t>(lane) * 128; o0 < warm_bytes;
+           o0 += kLines * kWave * 128) {
+        uint32_t v[kLines];
+#pragma unroll
+        for (int u = 0; u < kLines; ++u) {
+          const int64_t o = o0 + static_cast<int64_t>(u) * kWave * 128;
+          v[u] = *reinterpret_cast<const uint32_t*>(base + min(o, warm_bytes - 8));
+        }
+#pragma unroll
+        for (int u = 0; u < kLines; ++u) warm_acc ^= v[u];
+      }
     }
     __syncthreads();
     if (b < nblk) ok = L.diag_ok[b & 1] != 0;
@@ -498,7 +518,9 @@ __device__ __forceinline__ void sweep_matrix(
   __shared__ __attribute__((aligned(16))) double tiles16[7 * TL];
   __shared__ double wmax[kSweepWaves];
   __shared__ int diag_ok[2];
-  __shared__ double ydir[16 * R];
+  // y with zero padding up to the last index the post-multiplication reads
+  constexpr int kYdir = 16 * R + kSweepWaves * kWave;
+  __shared__ double ydir[kYdir];
   __shared__ double ypart[kSweepWaves * kWave > 16 * R ? kSweepWaves * kWave : 16 * R];
   const SweepLds L{pan,           ybufw,          ybufp,    tiles16,  tiles16 + 2 * TL,
                    tiles16 + 4 * TL, tiles16 + 6 * TL, wmax, diag_ok, 16 * R * LD};
@@ -511,8 +533,10 @@ __device__ __forceinline__ void sweep_matrix(
   const bool postmul = solve_only && post != nullptr;
   double* yd = postmul ? ydir : nullptr;
   bool ok;
+  uint32_t warm_acc = 0;
   if (wave == 0)
-    ok = sweep_pivot_role<R>(L, npiv, lane);
+    ok = sweep_pivot_role<R>(L, npiv, lane, postmul ? post : nullptr,
+                             static_cast<int64_t>(npiv) * ldp * 8, warm_acc);
   else if (wave == 1)
     ok = sweep_update_role<R, 1, TO>(L, M, P, npiv, solve_only, lane, inv, ldo, dir_out, yd);
   else if (wave == 2)
@@ -520,39 +544,46 @@ __device__ __forceinline__ void sweep_matrix(
   else
     ok = sweep_update_role<R, 3, TO>(L, M, P, npiv, solve_only, lane, inv, ldo, dir_out, yd);
   if (postmul) {
-    __syncthreads();
     // dir_out[i] = sum_j post[j][i] y_j (post is symmetric): thread t owns
     // output i = t % kOut for the columns j = h, h + kGroups, ... with
     // h = t / kOut, so each j is one contiguous row segment across the
     // threads; kBatch loads per thread are issued before their products (one
     // memory round trip per batch), and the kGroups partial sums of an output
-    // are added in group order through LDS
+    // are added in group order through LDS.  y is zero past npiv, and rows
+    // past npiv - 1 are read as row npiv - 1, so the loop needs no branches.
     constexpr int kOut = 16 * R;
     constexpr int kGroups = (kSweepWaves * kWave) / kOut > 0 ? (kSweepWaves * kWave) / kOut : 1;
     constexpr int kPerThread = (kOut + kGroups - 1) / kGroups;
     constexpr int kBatch = kPerThread < 32 ? kPerThread : 32;
+    for (int j = npiv + static_cast<int>(threadIdx.x); j < kYdir; j += kSweepWaves * kWave)
+      ydir[j] = 0.0;
+    __syncthreads();
     const int t = threadIdx.x;
     const int i = t % kOut, h = t / kOut;
     double sum = 0.0;
     if (h < kGroups) {
       const int ic = min(i, npiv - 1);
+      const int32_t step = kGroups * static_cast<int32_t>(ldp);
+      const int32_t last = (npiv - 1) * static_cast<int32_t>(ldp) + ic;
+      int32_t off = h * static_cast<int32_t>(ldp) + ic;
+      const double* yh = ydir + h;
 #pragma unroll 1
       for (int q0 = 0; q0 < kPerThread; q0 += kBatch) {
         double v[kBatch];
 #pragma unroll
         for (int q = 0; q < kBatch; ++q) {
-          const int j = h + kGroups * (q0 + q);
-          v[q] = post[static_cast<int64_t>(min(j, npiv - 1)) * ldp + ic];
+          v[q] = post[min(off, last)];
+          off += step;
         }
 #pragma unroll
-        for (int q = 0; q < kBatch; ++q) {
-          const int j = h + kGroups * (q0 + q);
-          sum = fma(v[q], j < npiv ? ydir[j] : 0.0, sum);
-        }
+        for (int q = 0; q < kBatch; ++q) sum = fma(v[q], yh[kGroups * q], sum);
+        yh += kGroups * kBatch;
       }
       ypart[h * kOut + i] = sum;
     }
     __syncthreads();
+    // (never true: keeps the warm-up loads of wave 0)
+    if (warm_acc == 0x2545F491u && npiv < 0) dir_out[0] = TO(0);
     if (t < npiv) {
       double d = ypart[t];
 #pragma unroll

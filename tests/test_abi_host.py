@@ -170,6 +170,25 @@ def test_mlp_entry_points_reject_bad_arguments():
     assert lib.gnmppi_mlp_adam(10, 0x10, 0x20, 0x30, 0x40, 0x50, 1e-3, 1.0, 0.999, 1e-8, 1, None) == _lib.EINVAL
 
 
+def test_sample_rollout_rejects_bad_arguments():
+    lib = _lib.load()
+    p = _problem()
+    K = 64
+
+    def call(W=0x30, ldw=K, K=K, anti=1, sigma=0.3, R=0x40, C=None, r0=None, c0=None, U=0x20):
+        return lib.gnmppi_sample_rollout(ctypes.byref(p), 0x10, U, sigma, 1, 0, anti, W, ldw, K, R,
+                                         K, C, r0, c0, None)
+
+    assert call(W=None) == _lib.EINVAL          # W is the sampler's output
+    assert call(U=None) == _lib.EINVAL
+    assert call(ldw=K - 1) == _lib.EINVAL
+    assert call(K=63, ldw=64) == _lib.EINVAL    # antithetic pairs need even K
+    assert call(K=0) == _lib.EINVAL
+    assert call(sigma=float("nan")) == _lib.EINVAL
+    assert call(R=None, C=None) == _lib.EINVAL  # nothing wanted of the K columns
+    assert call(r0=0x50, c0=None) == _lib.EINVAL
+
+
 def test_ggn_direction_rejects_bad_arguments():
     lib = _lib.load()
     LS_READY = _lib.JAC_LS | _lib.JAC_GRAM_READY
