@@ -29,7 +29,7 @@ constexpr int kCus = 256;  // MI355X compute units: the persistent grids are siz
 
 // Steps of one iteration in launch order; each is split by its shape class.
 enum Step {
-  kSample, kGramW, kReduceG, kSweepG, kRollout, kNominal, kFused, kSplit, kContractS, kReduceS,
+  kSample, kGramW, kReduceG, kRollout, kNominal, kFused, kSplit, kContractS, kReduceS, kSweepG,
   kGramH, kReduceH, kSweepH, kLine, kSteps
 };
 
@@ -114,6 +114,8 @@ Plan make_plan(int count, const gnmppi_batch_instance* in, const gnmppi_batch_se
       d.split_len = spl * 32;
     }
     d.gsplit = 1;
+    // the fused kernel forms G = W W^T with S: n more rows per k-slice
+    d.grows = fused ? d.n : 0;
     d.gsplit_len = ksteps * 32;
     d.hsplit = std::max(1, std::min(16, cdiv(d.m, 128)));
     d.hchunk = cdiv(cdiv(d.m, d.hsplit), 4) * 4;
@@ -122,8 +124,8 @@ Plan make_plan(int count, const gnmppi_batch_instance* in, const gnmppi_batch_se
     d.seed = set->seed + static_cast<uint64_t>(i);
     pl.N_max = std::max(pl.N_max, d.N);
     tiles[kSample][i] = batch_sample_tiles(d.n, d.K);
-    tiles[kGramW][i] = batch_contract_row_blocks(d.n) * d.gsplit;
-    tiles[kReduceG][i] = d.n;
+    tiles[kGramW][i] = fused ? 0 : batch_contract_row_blocks(d.n) * d.gsplit;
+    tiles[kReduceG][i] = fused ? 0 : d.n;
     tiles[kSweepG][i] = 1;
     tiles[kRollout][i] = fused ? 0 : batch_rollout_tiles(d.M, d.K);
     tiles[kNominal][i] = fused ? 1 : 0;
@@ -131,7 +133,9 @@ Plan make_plan(int count, const gnmppi_batch_instance* in, const gnmppi_batch_se
     tiles[kSplit][i] = 0;  // the sampler writes the bf16 planes itself
     tiles[kContractS][i] = fused ? 0 : batch_bf16_row_blocks(d.m) * d.nsplit;
     // one k-slice: the partial sum already is S (no reduction)
-    tiles[kReduceS][i] = d.nsplit > 1 ? cdiv(d.m, 16) * cdiv(d.npad, 64) : 0;
+    // (with G rows the reduction also writes G in FP64, so it always runs)
+    tiles[kReduceS][i] =
+        d.nsplit > 1 || d.grows > 0 ? cdiv(d.m + d.grows, 16) * cdiv(d.npad, 64) : 0;
     tiles[kGramH][i] = d.hsplit;
     tiles[kReduceH][i] = d.n + 1;
     tiles[kSweepH][i] = 1;
@@ -208,10 +212,14 @@ Plan make_plan(int count, const gnmppi_batch_instance* in, const gnmppi_batch_se
     d.c0 = reinterpret_cast<float*>(take(sizeof(float)));
     d.dU = reinterpret_cast<float*>(take(sizeof(float) * d.n));
     d.part = reinterpret_cast<float*>(
-        take(sizeof(float) * static_cast<size_t>(d.nsplit) * d.m * d.npad));
-    d.S = d.nsplit > 1 ? reinterpret_cast<float*>(take(sizeof(float) * static_cast<size_t>(d.m) * d.npad))
-                       : d.part;
-    d.gpart = reinterpret_cast<float*>(take(sizeof(float) * static_cast<size_t>(d.gsplit) * d.n * d.npad));
+        take(sizeof(float) * static_cast<size_t>(d.nsplit) * (d.m + d.grows) * d.npad));
+    d.S = d.nsplit > 1 || d.grows > 0
+              ? reinterpret_cast<float*>(take(sizeof(float) * static_cast<size_t>(d.m) * d.npad))
+              : d.part;
+    d.gpart = d.grows > 0 ? nullptr
+                          : reinterpret_cast<float*>(take(sizeof(float) *
+                                                          static_cast<size_t>(d.gsplit) * d.n *
+                                                          d.npad));
     d.Ginv = reinterpret_cast<float*>(take(sizeof(float) * d.n * d.npad));
     d.Wh = reinterpret_cast<__bf16*>(take(2 * static_cast<size_t>(d.n) * d.kpad));
     d.Wl = reinterpret_cast<__bf16*>(take(2 * static_cast<size_t>(d.n) * d.kpad));

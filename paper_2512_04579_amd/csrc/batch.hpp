@@ -21,6 +21,7 @@ struct BatchInst {
   int M, N, K, n, m;      // masses, horizon, samples, decisions 2N, residuals N (4M + 2)
   int npad, kpad;         // n rounded up to 16; K rounded up to 32
   int nsplit, split_len;  // k-slices of S = dR W^T
+  int grows;              // rows of G = W W^T below S in every k-slice (n, or 0)
   int gsplit, gsplit_len; // k-slices of G = W W^T
   int hchunk, hsplit;     // row chunks of [S r0]^T [S r0]
   int64_t ldw, ldr;       // leading dimensions of W (n x K) and R (m x K)

@@ -217,13 +217,15 @@ __global__ void __launch_bounds__(256) reduce_rows_vec_kernel(const float* __res
 }
 
 // Batched: the slices of every instance (the padding columns of every slice
-// are zero).
+// are zero), with the rows of G below those of S where the fused rollout
+// formed them.
 __global__ void __launch_bounds__(256) batch_reduce_rows_kernel(const BatchInst* __restrict__ inst,
                                                                 BatchLaunch L) {
   for (int w = blockIdx.x; w < L.count; w += gridDim.x) {
     const BatchItem it = L.items[w];
     const BatchInst& b = inst[it.inst];
-    reduce_rows_vec(b.part, b.nsplit, b.m, b.m, b.npad, 1.0, b.S, 0, nullptr, it.tile);
+    reduce_rows_vec(b.part, b.nsplit, b.m + b.grows, b.m, b.npad, 1.0, b.S, b.n,
+                    b.grows > 0 ? b.Gsum : nullptr, it.tile);
   }
 }
 

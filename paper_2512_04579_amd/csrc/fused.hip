@@ -239,7 +239,45 @@ __device__ __forceinline__ void fused_contract_role(const BatchInst& b, int item
   constexpr int DB = R * kDLd;
   const int ct = b.npad / 16;
   const int l16 = lane & 15, q = lane >> 4;
-  float* __restrict__ part = b.part + static_cast<int64_t>(item) * b.m * b.npad;
+  float* __restrict__ part = b.part + static_cast<int64_t>(item) * (b.m + b.grows) * b.npad;
+  // Row tile tr of this item's G = W W^T, 2 sum over its pairs w_s w_s^T
+  // (each pair's partner is -w_s), from the same bf16 planes (BF16x3), into
+  // the rows below S of the item's partial.  One row tile per step, so the
+  // work spreads over the first steps instead of delaying the first.
+  auto gram_row_tile = [&](int tr) {
+    f32x4 acc[kColSlots];
+#pragma unroll
+    for (int c = 0; c < kColSlots; ++c) acc[c] = f32x4{0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < kPairs / 32; ++kk) {
+      const int k0 = 32 * kk + 8 * q;
+      const bf16x8 ah = *reinterpret_cast<const bf16x8*>(wh + (16 * tr + l16) * kWLd + k0);
+      const bf16x8 al = *reinterpret_cast<const bf16x8*>(wl + (16 * tr + l16) * kWLd + k0);
+#pragma unroll
+      for (int c = 0; c < kColSlots; ++c) {
+        const int tc = mw + 4 * c;
+        if (tc < ct) {  // uniform
+          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(wh + (16 * tc + l16) * kWLd + k0);
+          const bf16x8 bl = *reinterpret_cast<const bf16x8*>(wl + (16 * tc + l16) * kWLd + k0);
+          acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[c], 0, 0, 0);
+          acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[c], 0, 0, 0);
+          acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[c], 0, 0, 0);
+        }
+      }
+    }
+    float* gdst = part + static_cast<int64_t>(b.m) * b.npad;
+#pragma unroll
+    for (int c = 0; c < kColSlots; ++c) {
+      const int tc = mw + 4 * c;
+      if (tc < ct) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = 16 * tr + 4 * q + e;
+          if (row < b.n) gdst[static_cast<int64_t>(row) * b.npad + 16 * tc + l16] = 2.0f * acc[c][e];
+        }
+      }
+    }
+  };
   for (int k = 0; k < b.N; ++k) {
     __syncthreads();  // step k's tile is complete
     const float* t = dbuf + (k & 1) * DB;
@@ -298,7 +336,10 @@ __device__ __forceinline__ void fused_contract_role(const BatchInst& b, int item
           }
         }
       }
+    if (b.grows > 0 && k < ct) gram_row_tile(k);
   }
+  if (b.grows > 0)
+    for (int tr = b.N; tr < ct; ++tr) gram_row_tile(tr);
 }
 
 // LDS of a block, sized for the longest chain (M = 16): the difference tile

@@ -157,11 +157,22 @@ __device__ __forceinline__ void drain_tile(const T (*t)[kSpb + 1], int nfr, int6
     // whole 4-sample chunks left of column K: one vector store each
     using V = T __attribute__((ext_vector_type(kVec)));
     const int nvec = min(kChunks, max(0, (K - col0) / kVec));  // uniform
-    for (int idx = tid; idx < nfr * kChunks; idx += kBlock) {
-      const int fr = idx / kChunks, ch = idx % kChunks, sv = ch * kVec;
-      if (ch < nvec)
-        *reinterpret_cast<V*>(R + (base + fr) * ldr + col0 + sv) =
-            V{t[fr][sv], t[fr][sv + 1], t[fr][sv + 2], t[fr][sv + 3]};
+    // a thread keeps one 4-sample chunk of every (kBlock / kChunks)-th row,
+    // so its LDS and HBM addresses advance by constant steps (the storing
+    // waves share their SIMDs with the rollout waves: few instructions per
+    // store)
+    const int ch = tid % kChunks, sv = ch * kVec;
+    if (ch < nvec) {
+      constexpr int kRowStep = kBlock / kChunks;
+      int fr = tid / kChunks;
+      const T* src = &t[fr][sv];
+      T* dst = R + (base + fr) * ldr + col0 + sv;
+      const int64_t dstep = static_cast<int64_t>(kRowStep) * ldr;
+      for (; fr < nfr; fr += kRowStep) {
+        *reinterpret_cast<V*>(dst) = V{src[0], src[1], src[2], src[3]};
+        src += kRowStep * (kSpb + 1);
+        dst += dstep;
+      }
     }
     // the block that holds column K: its last R columns one row per thread
     // (the bounds are uniform, so the stores need no divergent branches)
