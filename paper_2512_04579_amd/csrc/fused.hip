@@ -242,8 +242,10 @@ __device__ __forceinline__ void fused_contract_role(const BatchInst& b, int item
   float* __restrict__ part = b.part + static_cast<int64_t>(item) * (b.m + b.grows) * b.npad;
   // Row tile tr of this item's G = W W^T, 2 sum over its pairs w_s w_s^T
   // (each pair's partner is -w_s), from the same bf16 planes (BF16x3), into
-  // the rows below S of the item's partial.  One row tile per step, so the
-  // work spreads over the first steps instead of delaying the first.
+  // the rows below S of the item's partial: the tiles (tr, tc) with tc <= tr,
+  // each also stored transposed, so G is exactly symmetric.  One row tile
+  // per step, so the work spreads over the first steps instead of delaying
+  // the first.
   auto gram_row_tile = [&](int tr) {
     f32x4 acc[kColSlots];
 #pragma unroll
@@ -256,7 +258,7 @@ __device__ __forceinline__ void fused_contract_role(const BatchInst& b, int item
 #pragma unroll
       for (int c = 0; c < kColSlots; ++c) {
         const int tc = mw + 4 * c;
-        if (tc < ct) {  // uniform
+        if (tc <= tr) {  // uniform
           const bf16x8 bh = *reinterpret_cast<const bf16x8*>(wh + (16 * tc + l16) * kWLd + k0);
           const bf16x8 bl = *reinterpret_cast<const bf16x8*>(wl + (16 * tc + l16) * kWLd + k0);
           acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[c], 0, 0, 0);
@@ -269,11 +271,13 @@ __device__ __forceinline__ void fused_contract_role(const BatchInst& b, int item
 #pragma unroll
     for (int c = 0; c < kColSlots; ++c) {
       const int tc = mw + 4 * c;
-      if (tc < ct) {
+      if (tc <= tr) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int row = 16 * tr + 4 * q + e;
-          if (row < b.n) gdst[static_cast<int64_t>(row) * b.npad + 16 * tc + l16] = 2.0f * acc[c][e];
+          const int row = 16 * tr + 4 * q + e, col = 16 * tc + l16;
+          const float v = 2.0f * acc[c][e];
+          if (row < b.n) gdst[static_cast<int64_t>(row) * b.npad + col] = v;
+          if (tc < tr && col < b.n) gdst[static_cast<int64_t>(col) * b.npad + row] = v;
         }
       }
     }
