@@ -390,15 +390,17 @@ static void split_plan(int rows, int K, int step, int kw, int& nsplit_out, int& 
 }
 
 // k-split of the BF16 contraction: blocks of 64 kBf16RowTiles rows; aim at
-// two blocks per CU with at least four k-steps per block.
+// kBf16BlockTarget blocks with at least four k-steps per block, and a whole
+// number of turns of the kernel's load ring per slice.
 static void bf16_split_plan(int m, int K, int& nsplit_out, int& split_len_out) {
   const int row_blocks = (m + 64 * kBf16RowTiles - 1) / (64 * kBf16RowTiles);
   const int ksteps = (K + 31) / 32;
-  int nsplit = (768 + row_blocks - 1) / row_blocks;
+  int nsplit = (kBf16BlockTarget + row_blocks - 1) / row_blocks;
   const int max_split = ksteps / 4 > 1 ? ksteps / 4 : 1;
   if (nsplit > max_split) nsplit = max_split;
   if (nsplit < 1) nsplit = 1;
-  const int steps_per_split = (ksteps + nsplit - 1) / nsplit;
+  int steps_per_split = (ksteps + nsplit - 1) / nsplit;
+  steps_per_split = (steps_per_split + kBf16Depth - 1) / kBf16Depth * kBf16Depth;
   nsplit_out = (ksteps + steps_per_split - 1) / steps_per_split;
   split_len_out = steps_per_split * 32;
 }

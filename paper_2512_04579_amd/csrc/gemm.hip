@@ -314,15 +314,27 @@ __global__ void __launch_bounds__(256) batch_split_bf16_kernel(const BatchInst* 
 // CU traffic for B is a quarter of what per-wave loads would move; the LDS
 // stage is laid out [plane][k-group of 8][column] so that the 16 lanes of a
 // fragment read 256 contiguous bytes.  The A operand (fp32 residual rows)
-// streams from HBM into registers two steps ahead (kept raw until its step, so
-// no load is waited on early), is shifted by r0 and converted to bf16 (and
-// split into hi + lo) in registers.  One barrier per step.
+// streams from HBM into a ring of kBf16Depth register buffers (kept raw until
+// its step), is shifted by r0 and converted to bf16 (and split into hi + lo)
+// in registers; B is fetched two steps ahead into two register buffers and
+// written to LDS at the end of the step before its use.  One barrier per step.
+//
+// Every global load is unconditional: a load whose k-group lies past the end
+// of the slice reads the slice's first group instead (zeroed where it is
+// converted), and the loop runs a whole number of ring turns, the steps past
+// the slice contributing zeros.  Loads are then counted in program order, so
+// each step waits only for its own data and not for the ones in flight
+// behind it.
+//
+// VEC: 16-byte loads of 8 consecutive values of A (and of W with WF32);
+// needs 16-byte aligned rows whose allocation holds whole 8-value groups
+// (K % 8 == 0 for the single-instance layout; the batched rows are padded to
+// 64 values).  Otherwise one clamped load per value.
 //
 // WF32: B comes from the FP32 W itself (Wf, leading dimension ldw; Bh, Bl
-// unused) and is rounded (TERMS = 1) or split into hi + lo (TERMS = 3) on
-// its way into LDS -- the same arithmetic as the split pass, without it.
-// Each thread then loads 8-value pieces of W rows (two 16-byte loads when
-// wvec: ldw % 4 == 0 and Wf 16-byte aligned) and writes both planes.
+// unused) and is rounded (TERMS = 1) or split into hi + lo (TERMS = 3) on its
+// way into LDS -- the same arithmetic as the split pass, without it.  Without
+// WF32, B comes from the bf16 planes (Bh, Bl: n x kpad, zero past K).
 using f32x8 = float __attribute__((ext_vector_type(8)));
 // With WF32, rows m .. arows - 1 of A are the rows of W (Wf, no r0 shift),
 // so that the same launch also forms the partials of G = W W^T.
@@ -331,10 +343,12 @@ __device__ __forceinline__ void contract_bf16_block(
     int m, int n, int K, const float* __restrict__ R, int64_t ldr, const float* __restrict__ r0,
     const __bf16* __restrict__ Bh, const __bf16* __restrict__ Bl, int kpad, int split_len,
     float* __restrict__ part, int npad, int bx, int by, const float* __restrict__ Wf = nullptr,
-    int64_t ldw = 0, bool wvec = false, int arows = -1) {
+    int64_t ldw = 0, int arows = -1) {
   if (!WF32 || arows < m) arows = m;
   constexpr int PLANES = TERMS == 3 ? 2 : 1;
   constexpr int NCOL = 16 * NT;
+  constexpr int D = kBf16Depth;
+  static_assert(D % 2 == 0, "the ring turn covers both B buffers");
   // pieces per stage: 16-byte bf16 pieces of each plane, or 8-value FP32
   // pieces that yield both planes
   constexpr int CHUNKS = (WF32 ? 1 : PLANES) * NCOL * (kBf16Step / 8);
@@ -363,9 +377,12 @@ __device__ __forceinline__ void contract_bf16_block(
     }
   }
   // the B pieces this thread copies: piece c -> (plane, column, k-group),
-  // k-group fastest so that 8 neighbouring threads read one 128-byte run
+  // k-group fastest so that 8 neighbouring threads read one 128-byte run;
+  // pieces of the padding columns (and past CHUNKS) read column 0 and are
+  // not stored
   const __bf16* bsrc[PER_THREAD];
   const float* wsrc[PER_THREAD];
+  int bkg[PER_THREAD];
   bool bvalid[PER_THREAD];
 #pragma unroll
   for (int i = 0; i < PER_THREAD; ++i) {
@@ -373,44 +390,55 @@ __device__ __forceinline__ void contract_bf16_block(
     const int kg = c % (kBf16Step / 8), col = (c / (kBf16Step / 8)) % NCOL;
     const int pl = c / (NCOL * (kBf16Step / 8));
     bvalid[i] = c < CHUNKS && col < n;
+    bkg[i] = 8 * kg;
     const int64_t cc = col < n ? col : 0;
     if constexpr (WF32)
-      wsrc[i] = Wf + cc * ldw + 8 * kg;
+      wsrc[i] = Wf + cc * ldw;
     else
-      bsrc[i] = (pl == 0 ? Bh : Bl) + cc * kpad + 8 * kg;
+      bsrc[i] = (PLANES == 2 && pl == 1 ? Bl : Bh) + cc * kpad;
   }
   auto load_b = [&](int k0, BReg (&reg)[PER_THREAD]) {
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
-      if constexpr (WF32) {
-        // 8 values of W at k = k0 + 8 kg + e, zero at k >= K
-        const int kk = k0 + 8 * ((tid + 256 * i) % (kBf16Step / 8));
-        f32x8 v = f32x8{0, 0, 0, 0, 0, 0, 0, 0};
-        if (bvalid[i]) {
-          if (wvec && kk + 8 <= K) {
-            const f32x4 x0 = *reinterpret_cast<const f32x4*>(wsrc[i] + k0);
-            const f32x4 x1 = *reinterpret_cast<const f32x4*>(wsrc[i] + k0 + 4);
+      const int kk = k0 + bkg[i];
+      const int kc = kk < kend ? kk : kbeg + bkg[i];
+      if constexpr (WF32 && VEC) {
+        const f32x4 x0 = *reinterpret_cast<const f32x4*>(wsrc[i] + kc);
+        const f32x4 x1 = *reinterpret_cast<const f32x4*>(wsrc[i] + kc + 4);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              v[e] = x0[e];
-              v[4 + e] = x1[e];
-            }
-          } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = kk + e < K ? wsrc[i][k0 + e] : 0.0f;
-          }
+        for (int e = 0; e < 4; ++e) {
+          reg[i][e] = x0[e];
+          reg[i][4 + e] = x1[e];
         }
-        reg[i] = v;
+      } else if constexpr (WF32) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) reg[i][e] = wsrc[i][min(kc + e, K - 1)];
       } else {
-        reg[i] = bvalid[i] ? *reinterpret_cast<const bf16x8*>(bsrc[i] + k0) : bf16x8{};
+        reg[i] = *reinterpret_cast<const bf16x8*>(bsrc[i] + kc);
       }
     }
   };
+  // the padding columns' pieces hold zeros in both buffers from the start
+  // and are never written again
+#pragma unroll
+  for (int i = 0; i < PER_THREAD; ++i) {
+    const int c = tid + 256 * i;
+    if (c < CHUNKS && !bvalid[i]) {
+      const int kg = c % (kBf16Step / 8), col = (c / (kBf16Step / 8)) % NCOL;
+#pragma unroll
+      for (int pl = 0; pl < PLANES; ++pl) {
+        if (WF32 || pl == c / (NCOL * (kBf16Step / 8))) {
+          stage[0][pl][kg][col] = bf16x8{};
+          stage[1][pl][kg][col] = bf16x8{};
+        }
+      }
+    }
+  }
   auto store_b = [&](int buf, const BReg (&reg)[PER_THREAD]) {
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int c = tid + 256 * i;
-      if (c < CHUNKS) {
+      if (bvalid[i]) {
         const int kg = c % (kBf16Step / 8), col = (c / (kBf16Step / 8)) % NCOL;
         if constexpr (WF32) {
           bf16x8 h, l;
@@ -428,16 +456,17 @@ __device__ __forceinline__ void contract_bf16_block(
       }
     }
   };
-  // this lane's 8 raw A values of row tile t for the step at k0 (zero past
-  // kend); the r0 shift is applied where they are used, so that nothing waits
-  // on the loads before the step that consumes them
+  // this lane's 8 raw A values of row tile t for the step at k0 (a group past
+  // the slice reads the slice's first group); the r0 shift and the zeros past
+  // kend are applied where they are used
   auto load_a = [&](int k0, float (&a)[TM][8]) {
     const int kl = k0 + 8 * kq;
-    if (VEC && k0 + kBf16Step <= kend) {
+    const int kc = kl < kend ? kl : kbeg + 8 * kq;
+    if constexpr (VEC) {
 #pragma unroll
       for (int t = 0; t < TM; ++t) {
-        const f32x4 x0 = *reinterpret_cast<const f32x4*>(arow[t] + kl);
-        const f32x4 x1 = *reinterpret_cast<const f32x4*>(arow[t] + kl + 4);
+        const f32x4 x0 = *reinterpret_cast<const f32x4*>(arow[t] + kc);
+        const f32x4 x1 = *reinterpret_cast<const f32x4*>(arow[t] + kc + 4);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           a[t][e] = x0[e];
@@ -445,10 +474,11 @@ __device__ __forceinline__ void contract_bf16_block(
         }
       }
     } else {
+      // one value per load, each clamped into the row
 #pragma unroll
       for (int t = 0; t < TM; ++t)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) a[t][e] = (kl + e < kend) ? arow[t][kl + e] : 0.0f;
+        for (int e = 0; e < 8; ++e) a[t][e] = arow[t][min(kc + e, K - 1)];
     }
   };
 
@@ -458,56 +488,70 @@ __device__ __forceinline__ void contract_bf16_block(
 #pragma unroll
     for (int tn = 0; tn < NT; ++tn) acc[t][tn] = f32x4{0, 0, 0, 0};
 
-  if (nstep > 0) {
-    // A two steps ahead (HBM latency), B one step ahead (L2 -> LDS)
-    BReg breg[PER_THREAD];
-    float a0[TM][8], a1[TM][8];
-    load_b(kbeg, breg);
-    load_a(kbeg, a0);
-    if (nstep > 1) load_a(kbeg + kBf16Step, a1);
-    store_b(0, breg);
+  // A(s) sits in ring slot s % D and is reloaded with A(s + D) once it has
+  // been converted; B(s + 2) is fetched into buffer s % 2 at the start of
+  // step s, and B(s + 1) (fetched at step s - 1) goes to LDS at its end
+  if (nstep > 0) {  // uniform
+    float a[D][TM][8];
+    BReg breg[2][PER_THREAD];
+    load_b(kbeg, breg[0]);
+#pragma unroll
+    for (int d = 0; d < D; ++d) load_a(kbeg + d * kBf16Step, a[d]);
+    load_b(kbeg + kBf16Step, breg[1]);
+    store_b(0, breg[0]);
     __syncthreads();
-    for (int s = 0; s < nstep; ++s) {
-      const int k0 = kbeg + s * kBf16Step;
-      const bool more = s + 1 < nstep;
-      float a2[TM][8];
-      if (more) load_b(k0 + kBf16Step, breg);
-      if (s + 2 < nstep) load_a(k0 + 2 * kBf16Step, a2);
-      const int buf = s & 1;
+    auto step = [&](int k0, float (&as)[TM][8], BReg (&bnext)[PER_THREAD],
+                    BReg (&bstore)[PER_THREAD], int buf) {
+      load_b(k0 + 2 * kBf16Step, bnext);
       const int kl = k0 + 8 * kq;
       bf16x8 ah[TM], al[TM];
+      if (k0 + kBf16Step <= kend) {  // uniform: a whole step inside the slice
 #pragma unroll
-      for (int t = 0; t < TM; ++t)
+        for (int t = 0; t < TM; ++t)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const float v = (kl + e < kend) ? a0[t][e] - asub[t] : 0.0f;
-          ah[t][e] = static_cast<__bf16>(v);
-          if constexpr (TERMS == 3) al[t][e] = static_cast<__bf16>(v - static_cast<float>(ah[t][e]));
-        }
+          for (int e = 0; e < 8; ++e) {
+            const float v = as[t][e] - asub[t];
+            ah[t][e] = static_cast<__bf16>(v);
+            if constexpr (TERMS == 3)
+              al[t][e] = static_cast<__bf16>(v - static_cast<float>(ah[t][e]));
+          }
+      } else {
+#pragma unroll
+        for (int t = 0; t < TM; ++t)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const float v = (kl + e < kend) ? as[t][e] - asub[t] : 0.0f;
+            ah[t][e] = static_cast<__bf16>(v);
+            if constexpr (TERMS == 3)
+              al[t][e] = static_cast<__bf16>(v - static_cast<float>(ah[t][e]));
+          }
+      }
+      load_a(k0 + D * kBf16Step, as);
 #pragma unroll
       for (int tn = 0; tn < NT; ++tn) {
         const bf16x8 bh = stage[buf][0][kq][16 * tn + r16];
 #pragma unroll
         for (int t = 0; t < TM; ++t)
-          acc[t][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[t], bh, acc[t][tn], 0, 0, 0);
+          acc[t][tn] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[t], bh, acc[t][tn], 0, 0, 0);
         if constexpr (TERMS == 3) {
           const bf16x8 bl = stage[buf][PLANES - 1][kq][16 * tn + r16];
 #pragma unroll
           for (int t = 0; t < TM; ++t) {
-            acc[t][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[t], bl, acc[t][tn], 0, 0, 0);
-            acc[t][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[t], bh, acc[t][tn], 0, 0, 0);
+            acc[t][tn] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[t], bl, acc[t][tn], 0, 0, 0);
+            acc[t][tn] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[t], bh, acc[t][tn], 0, 0, 0);
           }
         }
       }
-      if (more) store_b(buf ^ 1, breg);
-#pragma unroll
-      for (int t = 0; t < TM; ++t)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          a0[t][e] = a1[t][e];
-          a1[t][e] = a2[t][e];
-        }
+      store_b(buf ^ 1, bstore);
       __syncthreads();
+    };
+    for (int s = 0; s < nstep; s += D) {
+#pragma unroll
+      for (int d = 0; d < D; ++d)
+        step(kbeg + (s + d) * kBf16Step, a[d], breg[d & 1], breg[(d + 1) & 1], d & 1);
     }
   }
   float* out = part + static_cast<int64_t>(by) * arows * npad;
@@ -525,11 +569,10 @@ __device__ __forceinline__ void contract_bf16_block(
 template <int TERMS, int NT, int TM, bool VEC>
 __global__ void __launch_bounds__(256) contract_bf16_kernel(
     int m, int n, int K, const float* __restrict__ R, int64_t ldr, const float* __restrict__ r0,
-    const float* __restrict__ Wf, int64_t ldw, bool wvec, int split_len, float* __restrict__ part,
+    const float* __restrict__ Wf, int64_t ldw, int split_len, float* __restrict__ part,
     int npad, int arows) {
   contract_bf16_block<TERMS, NT, TM, VEC, true>(m, n, K, R, ldr, r0, nullptr, nullptr, 0, split_len,
-                                                part, npad, blockIdx.x, blockIdx.y, Wf, ldw, wvec,
-                                                arows);
+                                                part, npad, blockIdx.x, blockIdx.y, Wf, ldw, arows);
 }
 
 // Batched S = (R - r0 1^T) W^T partials, BF16x3; tile = split * row_blocks + row block.
@@ -549,12 +592,12 @@ __global__ void __launch_bounds__(256) batch_contract_bf16_kernel(const BatchIns
 
 template <int TERMS, bool VEC>
 hipError_t bf16_dispatch(int nt, dim3 grid, hipStream_t st, int m, int n, int K, const float* R,
-                         int64_t ldr, const float* r0, const float* W, int64_t ldw, bool wvec,
+                         int64_t ldr, const float* r0, const float* W, int64_t ldw,
                          int split_len, float* part, int npad, int arows) {
 #define GNM_BF_CASE(NT)                                                                        \
   case NT:                                                                                     \
     hipLaunchKernelGGL((contract_bf16_kernel<TERMS, NT, kBf16RowTiles, VEC>), grid, dim3(256), 0, \
-                       st, m, n, K, R, ldr, r0, W, ldw, wvec, split_len, part, npad, arows);   \
+                       st, m, n, K, R, ldr, r0, W, ldw, split_len, part, npad, arows);         \
     break;
   switch (nt) {
     GNM_BF_CASE(1) GNM_BF_CASE(2) GNM_BF_CASE(3) GNM_BF_CASE(4) GNM_BF_CASE(5) GNM_BF_CASE(6)
@@ -635,19 +678,19 @@ hipError_t launch_contract_bf16(int terms, int m, int n, int K, const float* R, 
   const int arows = with_gram ? m + n : m;
   dim3 grid((arows + 64 * kBf16RowTiles - 1) / (64 * kBf16RowTiles), nsplit);
   const int nt = (n + 15) / 16;
-  const bool wvec = (ldw % 4 == 0) && (reinterpret_cast<uintptr_t>(W) % 16 == 0);
-  // the vector A loads need aligned rows of R (and of W when it is part of A)
+  // 16-byte loads of whole 8-value groups: aligned rows of R and W, and K % 8
+  // == 0 so that no group runs past the end of a row
   const bool vec = (ldr % 4 == 0) && (reinterpret_cast<uintptr_t>(R) % 16 == 0) &&
-                   (!with_gram || wvec);
+                   (ldw % 4 == 0) && (reinterpret_cast<uintptr_t>(W) % 16 == 0) && (K % 8 == 0);
   if (terms == 3)
-    return vec ? bf16_dispatch<3, true>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, wvec, split_len,
-                                        part, npad, arows)
-               : bf16_dispatch<3, false>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, wvec,
-                                         split_len, part, npad, arows);
-  return vec ? bf16_dispatch<1, true>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, wvec, split_len,
-                                      part, npad, arows)
-             : bf16_dispatch<1, false>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, wvec, split_len,
-                                       part, npad, arows);
+    return vec ? bf16_dispatch<3, true>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, split_len, part,
+                                        npad, arows)
+               : bf16_dispatch<3, false>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, split_len, part,
+                                         npad, arows);
+  return vec ? bf16_dispatch<1, true>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, split_len, part,
+                                      npad, arows)
+             : bf16_dispatch<1, false>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, split_len, part,
+                                       npad, arows);
 }
 
 }  // namespace gnm

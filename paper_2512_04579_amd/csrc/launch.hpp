@@ -63,6 +63,11 @@ int contract_kw(size_t elem_size, int ncol);
 // launch_contract_bf16: 16-row MFMA tiles per wave (a block covers 64 times
 // as many rows) and the planner's target for its blocks per k-slice.
 constexpr int kBf16RowTiles = 1;
+// k-steps that the BF16 contraction's A loads run ahead of their use (an
+// even number: the loop turns over the A ring and both B buffers together).
+constexpr int kBf16Depth = 2;
+// Blocks the planner aims at for one BF16 contraction (row blocks x k-slices).
+constexpr int kBf16BlockTarget = 768;
 // The batched contraction (throughput-bound, plenty of blocks) takes two
 // row tiles per wave: each staged B fragment then feeds twice the MFMAs.
 constexpr int kBatchBf16RowTiles = 2;
