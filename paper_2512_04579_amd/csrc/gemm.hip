@@ -321,8 +321,9 @@ __global__ void __launch_bounds__(256) batch_split_bf16_kernel(const BatchInst* 
 //
 // Every global load is unconditional: a load whose k-group lies past the end
 // of the slice reads the slice's first group instead (zeroed where it is
-// converted), and the loop runs a whole number of ring turns, the steps past
-// the slice contributing zeros.  Loads are then counted in program order, so
+// converted; that group lies inside the row even when the slice holds fewer
+// than 32 values), and the loop runs a whole number of ring turns, the steps
+// past the slice contributing zeros.  Loads are then counted in program order, so
 // each step waits only for its own data and not for the ones in flight
 // behind it.
 //
@@ -401,7 +402,7 @@ __device__ __forceinline__ void contract_bf16_block(
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int kk = k0 + bkg[i];
-      const int kc = kk < kend ? kk : kbeg + bkg[i];
+      const int kc = kk < kend ? kk : kbeg;
       if constexpr (WF32 && VEC) {
         const f32x4 x0 = *reinterpret_cast<const f32x4*>(wsrc[i] + kc);
         const f32x4 x1 = *reinterpret_cast<const f32x4*>(wsrc[i] + kc + 4);
@@ -461,7 +462,7 @@ __device__ __forceinline__ void contract_bf16_block(
   // kend are applied where they are used
   auto load_a = [&](int k0, float (&a)[TM][8]) {
     const int kl = k0 + 8 * kq;
-    const int kc = kl < kend ? kl : kbeg + 8 * kq;
+    const int kc = kl < kend ? kl : kbeg;
     if constexpr (VEC) {
 #pragma unroll
       for (int t = 0; t < TM; ++t) {

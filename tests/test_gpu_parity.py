@@ -416,6 +416,31 @@ def test_jacobian_bf16x3_split_keeps_fp32_accuracy(case, method):
     assert e < 2e-5, e
 
 
+def _linear_residuals(m, n, K, seed):
+    # residual columns exactly linear in the perturbations, R[:, 1 + s] = r0 + A W[:, s]
+    rng = np.random.default_rng(seed)
+    W = rnd(0.3 * rng.standard_normal((n, K)), "f32")
+    A = rng.standard_normal((m, n))
+    r0 = rng.standard_normal(m)
+    return rnd(np.concatenate([r0[:, None], r0[:, None] + A @ W], axis=1), "f32"), W
+
+
+@pytest.mark.parametrize("n,K", [(5, 8), (5, 40), (37, 904), (37, 1000), (37, 4104)])
+def test_bf16x3_contraction_with_a_ragged_last_step(n, K):
+    # K % 8 == 0 takes the 16-byte load path; K % 32 != 0 leaves a last k-step
+    # with fewer than 32 values, whose missing groups must read inside the row
+    # (tight rows: the last row ends the allocation) and contribute zeros
+    R, W = _linear_residuals(300, n, K, seed=K)
+    code = _lib.JAC_LS | _lib.JAC_BF16X3
+    J, st = _run_jacobian(R, W, "f32", code, ldw=K, ldr=K)
+    assert st == _lib.OK
+    assert_parity(J, jacobian.ls(R, W), "f32", f"J (bf16x3, K={K}, tight rows)")
+    dU, st2 = _run_direction(R, W, "f32", code)
+    assert st2 == [0, 0]
+    assert_parity(dU, ggn.direction(jacobian.ls(R, W), R[:, 0], 0.0), "f32",
+                  f"dU (bf16x3, K={K}, NaN past K in every row)")
+
+
 def test_jacobian_bf16_precision_split_error_is_bounded():
     # plain BF16 operands: the error is the precision split's, reported, not FP32 parity
     prob, dtype, K, sigma, R, W = _jacobian_inputs("c2")
