@@ -93,6 +93,15 @@ struct CtrlLineStaged {
 
 // ---- chain ---------------------------------------------------------------
 
+// a - b, never fused with a product that produces b: keeps the neighbour
+// tension's row shift foldable into the subtraction (v_sub_f32 with a DPP
+// operand) instead of a separate DPP move feeding a fused multiply-add.
+template <typename T>
+__device__ __forceinline__ T sub_unfused(T a, T b) {
+#pragma clang fp contract(off)
+  return a - b;
+}
+
 // Right-hand side for mass i (lane i of the group).  The end mass moves with
 // the commanded velocity: its lane enters every step with v = u and inverse
 // mass im = 0, so dv = 0 keeps v = u through the RK4 stages and dp = v is
@@ -125,8 +134,8 @@ __device__ __forceinline__ void chain_rhs(T px, T py, T vx, T vy, const ChainDev
   }
   dpx = vx;
   dpy = vy;
-  dvx = (nx - tx) * im;
-  dvy = (ny - ty) * im;
+  dvx = sub_unfused(nx, tx) * im;
+  dvy = sub_unfused(ny, ty) * im;
   if constexpr (G < 16) {
     dvx = free_mass ? dvx : T(0);
     dvy = free_mass ? dvy : T(0);
