@@ -102,17 +102,20 @@ __device__ __forceinline__ T sub_unfused(T a, T b) {
   return a - b;
 }
 
-// Right-hand side for mass i (lane i of the group).  The end mass moves with
-// the commanded velocity: its lane enters every step with v = u and inverse
-// mass im = 0, so dv = 0 keeps v = u through the RK4 stages and dp = v is
-// the commanded velocity with no per-stage select.  With G < 16 the last
-// lane of a group reads T_{i+1} from the first lane of the next sample's
-// group, which may be infinite if that sample diverged; inf * 0 would carry a
-// NaN into this sample, so lanes without a free mass select dv = 0 there (a
-// select, so finite results are unchanged bit for bit).
+// Right-hand side for mass i (lane i of the group): dp = v, and the tension
+// difference f = T_{i+1} - T_i, whose product with the lane's inverse mass is
+// dv; the caller folds the inverse mass into its step constants, so the
+// stages carry f and no multiply per stage.  The end mass moves with the
+// commanded velocity: its lane enters every step with v = u and inverse mass
+// 0, so the stages keep v = u and dp = v is the commanded velocity with no
+// per-stage select.  With G < 16 the last lane of a group reads T_{i+1} from
+// the first lane of the next sample's group, which may be infinite if that
+// sample diverged; inf * 0 would carry a NaN into this sample, so lanes
+// without a free mass select f = 0 there (a select, so finite results are
+// unchanged bit for bit).
 template <typename T, int G>
 __device__ __forceinline__ void chain_rhs(T px, T py, T vx, T vy, const ChainDev<T>& cd, bool first,
-                                          bool free_mass, T im, T& dpx, T& dpy, T& dvx, T& dvy) {
+                                          bool free_mass, T& dpx, T& dpy, T& fx, T& fy) {
   T qx = 0, qy = 0;
   if constexpr (G > 1) {
     qx = dpp_move<kDppRowShr1>(px);
@@ -134,11 +137,11 @@ __device__ __forceinline__ void chain_rhs(T px, T py, T vx, T vy, const ChainDev
   }
   dpx = vx;
   dpy = vy;
-  dvx = sub_unfused(nx, tx) * im;
-  dvy = sub_unfused(ny, ty) * im;
+  fx = sub_unfused(nx, tx);
+  fy = sub_unfused(ny, ty);
   if constexpr (G < 16) {
-    dvx = free_mass ? dvx : T(0);
-    dvy = free_mass ? dvy : T(0);
+    fx = free_mass ? fx : T(0);
+    fy = free_mass ? fy : T(0);
   }
 }
 
@@ -309,7 +312,11 @@ __device__ __forceinline__ T chain_rollout(const ChainDev<T>& cd, int N,
   const T rvx = xref[2 * M + 2 * ii], rvy = xref[2 * M + 2 * ii + 1];
   const T wu0 = dsqrt(T(2) * r[0]), wu1 = dsqrt(T(2) * r[1]);
   const T h = cd.dt, hh = T(0.5) * cd.dt, h6 = cd.dt / T(6);
+  // the step constants of the velocity times the lane's inverse mass (0 for
+  // the end mass and the padding lanes): the stages carry the tension
+  // differences f, and dv = f / mass enters only through these
   const T im = free_mass ? cd.inv_mass : T(0);
+  const T h_im = h * im, hh_im = hh * im, h6_im = h6 * im;
   T cost = 0;
   for (int k0 = 0; k0 < N; k0 += 4) {
 #pragma unroll
@@ -322,21 +329,22 @@ __device__ __forceinline__ T chain_rollout(const ChainDev<T>& cd, int N,
         vy = u1;
       }
       T a_px, a_py, a_vx, a_vy, b_px, b_py, b_vx, b_vy;
-      chain_rhs<T, G>(px, py, vx, vy, cd, first, free_mass, im, a_px, a_py, a_vx, a_vy);
+      // a_v*, b_v*: tension differences (dv times the mass)
+      chain_rhs<T, G>(px, py, vx, vy, cd, first, free_mass, a_px, a_py, a_vx, a_vy);
       T s_px = a_px, s_py = a_py, s_vx = a_vx, s_vy = a_vy;  // running k1 + 2 k2 + 2 k3 + k4
-      chain_rhs<T, G>(px + hh * a_px, py + hh * a_py, vx + hh * a_vx, vy + hh * a_vy, cd, first,
-                      free_mass, im, b_px, b_py, b_vx, b_vy);
+      chain_rhs<T, G>(px + hh * a_px, py + hh * a_py, vx + hh_im * a_vx, vy + hh_im * a_vy, cd,
+                      first, free_mass, b_px, b_py, b_vx, b_vy);
       s_px += T(2) * b_px; s_py += T(2) * b_py; s_vx += T(2) * b_vx; s_vy += T(2) * b_vy;
-      chain_rhs<T, G>(px + hh * b_px, py + hh * b_py, vx + hh * b_vx, vy + hh * b_vy, cd, first,
-                      free_mass, im, a_px, a_py, a_vx, a_vy);
+      chain_rhs<T, G>(px + hh * b_px, py + hh * b_py, vx + hh_im * b_vx, vy + hh_im * b_vy, cd,
+                      first, free_mass, a_px, a_py, a_vx, a_vy);
       s_px += T(2) * a_px; s_py += T(2) * a_py; s_vx += T(2) * a_vx; s_vy += T(2) * a_vy;
-      chain_rhs<T, G>(px + h * a_px, py + h * a_py, vx + h * a_vx, vy + h * a_vy, cd, first,
-                      free_mass, im, b_px, b_py, b_vx, b_vy);
+      chain_rhs<T, G>(px + h * a_px, py + h * a_py, vx + h_im * a_vx, vy + h_im * a_vy, cd, first,
+                      free_mass, b_px, b_py, b_vx, b_vy);
       s_px += b_px; s_py += b_py; s_vx += b_vx; s_vy += b_vy;
       px += h6 * s_px;
       py += h6 * s_py;
-      vx += h6 * s_vx;
-      vy += h6 * s_vy;
+      vx += h6_im * s_vx;
+      vy += h6_im * s_vy;
       const T e0 = wpx * (px - rpx), e1 = wpy * (py - rpy);
       const T e2 = wvx * (vx - rvx), e3 = wvy * (vy - rvy);
       const T f0 = wu0 * u0, f1 = wu1 * u1;
