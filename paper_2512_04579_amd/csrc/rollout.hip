@@ -308,8 +308,9 @@ __device__ __forceinline__ T chain_rollout(const ChainDev<T>& cd, int N,
   T vy = has_mass ? x0[2 * M + 2 * ii + 1] : T(0);
   const T wpx = dsqrt(T(2) * q[2 * ii]), wpy = dsqrt(T(2) * q[2 * ii + 1]);
   const T wvx = dsqrt(T(2) * q[2 * M + 2 * ii]), wvy = dsqrt(T(2) * q[2 * M + 2 * ii + 1]);
-  const T rpx = xref[2 * ii], rpy = xref[2 * ii + 1];
-  const T rvx = xref[2 * M + 2 * ii], rvy = xref[2 * M + 2 * ii + 1];
+  // residual w (x - x_ref) as one fused multiply-add: w x + (-w x_ref)
+  const T cpx = -wpx * xref[2 * ii], cpy = -wpy * xref[2 * ii + 1];
+  const T cvx = -wvx * xref[2 * M + 2 * ii], cvy = -wvy * xref[2 * M + 2 * ii + 1];
   const T wu0 = dsqrt(T(2) * r[0]), wu1 = dsqrt(T(2) * r[1]);
   const T h = cd.dt, hh = T(0.5) * cd.dt, h6 = cd.dt / T(6);
   // the step constants of the velocity times the lane's inverse mass (0 for
@@ -345,8 +346,8 @@ __device__ __forceinline__ T chain_rollout(const ChainDev<T>& cd, int N,
       py += h6 * s_py;
       vx += h6_im * s_vx;
       vy += h6_im * s_vy;
-      const T e0 = wpx * (px - rpx), e1 = wpy * (py - rpy);
-      const T e2 = wvx * (vx - rvx), e3 = wvy * (vy - rvy);
+      const T e0 = fma(wpx, px, cpx), e1 = fma(wpy, py, cpy);
+      const T e2 = fma(wvx, vx, cvx), e3 = fma(wvy, vy, cvy);
       const T f0 = wu0 * u0, f1 = wu1 * u1;
       if constexpr (COST) {
         if (has_mass) cost += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
