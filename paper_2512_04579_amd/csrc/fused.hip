@@ -53,22 +53,25 @@ struct FusedShape {
 };
 
 // One RK4 stage for a sample held in one lane.  The stage input is
-// (p, v) + c (kp, kv) with (kp, kv) the previous stage's derivative (zero
-// before the first stage); its derivative overwrites (kp, kv) and is added
-// to the running sums with weight wgt.  The chain's right-hand side: link
-// tension T_i = (k_lin + k_cub |d_i|^2) d_i with d_i = P_i - P_{i-1} (P_{-1}
-// the anchor at the origin); a free mass accelerates by (T_{i+1} - T_i) /
-// mass; the end mass (i = M - 1) moves with its velocity slot, which holds
-// the commanded velocity, and does not accelerate.  The masses are streamed
-// in order, so only two tensions are live at a time.
+// (p, v) + c (kp, kv / mass) with (kp, kv) the previous stage's derivative
+// (zero before the first stage), cim = c / mass; its derivative overwrites
+// (kp, kv) and is added to the running sums with weight wgt.  The chain's
+// right-hand side: link tension T_i = (k_lin + k_cub |d_i|^2) d_i with
+// d_i = P_i - P_{i-1} (P_{-1} the anchor at the origin); a free mass
+// accelerates by (T_{i+1} - T_i) / mass, and kv holds the tension difference
+// itself (every free mass has the same mass, which the caller folds into its
+// constants: no multiply per mass and stage); the end mass (i = M - 1) moves
+// with its velocity slot, which holds the commanded velocity, and does not
+// accelerate.  The masses are streamed in order, so only two tensions are
+// live at a time.
 template <int M>
 __device__ __forceinline__ void chain_stage_lane(const float (&px)[M], const float (&py)[M],
                                                  const float (&vx)[M], const float (&vy)[M],
                                                  float (&kpx)[M], float (&kpy)[M],
                                                  float (&kvx)[M], float (&kvy)[M], float (&spx)[M],
                                                  float (&spy)[M], float (&svx)[M],
-                                                 float (&svy)[M], float c, float wgt, float k_lin,
-                                                 float k_cub, float im) {
+                                                 float (&svy)[M], float c, float cim, float wgt,
+                                                 float k_lin, float k_cub) {
   float qx = 0.0f, qy = 0.0f;  // stage position of the previous mass (the anchor first)
   float tpx = 0.0f, tpy = 0.0f;
 #pragma unroll
@@ -79,9 +82,9 @@ __device__ __forceinline__ void chain_stage_lane(const float (&px)[M], const flo
     const float tx = s * dx, ty = s * dy;
     if (i > 0) {  // mass i - 1 is complete: it needed T_i
       const int j = i - 1;
-      const float nvx = (tx - tpx) * im, nvy = (ty - tpy) * im;
-      kpx[j] = vx[j] + c * kvx[j];
-      kpy[j] = vy[j] + c * kvy[j];
+      const float nvx = tx - tpx, nvy = ty - tpy;
+      kpx[j] = vx[j] + cim * kvx[j];
+      kpy[j] = vy[j] + cim * kvy[j];
       kvx[j] = nvx;
       kvy[j] = nvy;
       spx[j] += wgt * kpx[j];
@@ -95,8 +98,8 @@ __device__ __forceinline__ void chain_stage_lane(const float (&px)[M], const flo
     tpy = ty;
   }
   constexpr int j = M - 1;  // the end mass: no acceleration
-  kpx[j] = vx[j] + c * kvx[j];
-  kpy[j] = vy[j] + c * kvy[j];
+  kpx[j] = vx[j] + cim * kvx[j];
+  kpy[j] = vy[j] + cim * kvy[j];
   kvx[j] = 0.0f;
   kvy[j] = 0.0f;
   spx[j] += wgt * kpx[j];
@@ -118,20 +121,21 @@ __device__ __forceinline__ void chain_rk4_lane(float (&px)[M], float (&py)[M], f
     kpx[i] = kpy[i] = kvx[i] = kvy[i] = 0.0f;
     spx[i] = spy[i] = svx[i] = svy[i] = 0.0f;
   }
-  chain_stage_lane<M>(px, py, vx, vy, kpx, kpy, kvx, kvy, spx, spy, svx, svy, 0.0f, 1.0f, k_lin,
-                      k_cub, im);
-  chain_stage_lane<M>(px, py, vx, vy, kpx, kpy, kvx, kvy, spx, spy, svx, svy, hh, 2.0f, k_lin,
-                      k_cub, im);
-  chain_stage_lane<M>(px, py, vx, vy, kpx, kpy, kvx, kvy, spx, spy, svx, svy, hh, 2.0f, k_lin,
-                      k_cub, im);
-  chain_stage_lane<M>(px, py, vx, vy, kpx, kpy, kvx, kvy, spx, spy, svx, svy, h, 1.0f, k_lin,
-                      k_cub, im);
+  chain_stage_lane<M>(px, py, vx, vy, kpx, kpy, kvx, kvy, spx, spy, svx, svy, 0.0f, 0.0f, 1.0f,
+                      k_lin, k_cub);
+  chain_stage_lane<M>(px, py, vx, vy, kpx, kpy, kvx, kvy, spx, spy, svx, svy, hh, hh * im, 2.0f,
+                      k_lin, k_cub);
+  chain_stage_lane<M>(px, py, vx, vy, kpx, kpy, kvx, kvy, spx, spy, svx, svy, hh, hh * im, 2.0f,
+                      k_lin, k_cub);
+  chain_stage_lane<M>(px, py, vx, vy, kpx, kpy, kvx, kvy, spx, spy, svx, svy, h, h * im, 1.0f,
+                      k_lin, k_cub);
+  const float h6im = h6 * im;
 #pragma unroll
   for (int i = 0; i < M; ++i) {
     px[i] += h6 * spx[i];
     py[i] += h6 * spy[i];
-    vx[i] += h6 * svx[i];
-    vy[i] += h6 * svy[i];
+    vx[i] += h6im * svx[i];
+    vy[i] += h6im * svy[i];
   }
 }
 
