@@ -390,12 +390,17 @@ static void split_plan(int rows, int K, int step, int kw, int& nsplit_out, int& 
 }
 
 // k-split of the BF16 contraction: blocks of 64 kBf16RowTiles rows; aim at
-// kBf16BlockTarget blocks with at least four k-steps per block, and a whole
-// number of turns of the kernel's load ring per slice.
-static void bf16_split_plan(int m, int K, int& nsplit_out, int& split_len_out) {
+// kBf16BlockTarget blocks (terms = 3) or kBf16BlockTargetPlain (terms = 1,
+// a third of the MFMA work per step: fewer, longer blocks stream R better and
+// write fewer partials) with at least four k-steps per block, and a whole
+// number of turns of the kernel's load ring per slice.  The plain target is
+// the smaller one, so terms = 3 gives the larger split count.
+static void bf16_split_plan(int m, int K, int terms, int& nsplit_out, int& split_len_out) {
+  static_assert(kBf16BlockTargetPlain <= kBf16BlockTarget, "workspace sized for terms = 3");
   const int row_blocks = (m + 64 * kBf16RowTiles - 1) / (64 * kBf16RowTiles);
   const int ksteps = (K + 31) / 32;
-  int nsplit = (kBf16BlockTarget + row_blocks - 1) / row_blocks;
+  const int target = terms == 3 ? kBf16BlockTarget : kBf16BlockTargetPlain;
+  int nsplit = (target + row_blocks - 1) / row_blocks;
   const int max_split = ksteps / 4 > 1 ? ksteps / 4 : 1;
   if (nsplit > max_split) nsplit = max_split;
   if (nsplit < 1) nsplit = 1;
@@ -422,7 +427,7 @@ JacPlan jacobian_plan(int dtype, int m, int n, int K, int method) {
   int ns_max, sl_max, ns_m, sl_m, ns_b = 0, sl_b;
   split_plan(m + n, K, step, kw, ns_max, sl_max);
   split_plan(m, K, step, kw, ns_m, sl_m);
-  if (dtype == GNMPPI_F32) bf16_split_plan(m, K, ns_b, sl_b);
+  if (dtype == GNMPPI_F32) bf16_split_plan(m, K, 3, ns_b, sl_b);
   if (ns_m > ns_max) ns_max = ns_m;
   if (ns_b > ns_max) ns_max = ns_b;
   const size_t part_elems = static_cast<size_t>(ns_max) * (m + n) * p.npad;
@@ -436,7 +441,7 @@ JacPlan jacobian_plan(int dtype, int m, int n, int K, int method) {
   p.total = p.gpart_off + align_up(static_cast<size_t>(p.gsplit) * n * p.npad * esz);
   if (method & (GNMPPI_JAC_BF16 | GNMPPI_JAC_BF16X3)) {
     p.rows = m;  // G is formed by the FP32 W-only contraction
-    bf16_split_plan(m, K, p.nsplit, p.split_len);
+    bf16_split_plan(m, K, (method & GNMPPI_JAC_BF16X3) ? 3 : 1, p.nsplit, p.split_len);
   }
   return p;
 }
@@ -630,7 +635,7 @@ hipError_t ggn_direction_typed(int m, int n, int K, const T* R, int64_t ldr, con
   const int rows = with_gram ? m + n : m;
   int nsplit = 0, split_len = 0;
   if (bf16_terms)
-    bf16_split_plan(rows, K, nsplit, split_len);
+    bf16_split_plan(rows, K, bf16_terms, nsplit, split_len);
   else
     split_plan(rows, K, sizeof(T) == 4 ? 32 : 16, contract_kw(sizeof(T), n), nsplit, split_len);
   char* wk = static_cast<char*>(work);

@@ -66,8 +66,10 @@ constexpr int kBf16RowTiles = 1;
 // k-steps that the BF16 contraction's A loads run ahead of their use (an
 // even number: the loop turns over the A ring and both B buffers together).
 constexpr int kBf16Depth = 2;
-// Blocks the planner aims at for one BF16 contraction (row blocks x k-slices).
+// Blocks the planner aims at for one BF16 contraction (row blocks x k-slices):
+// BF16x3 (three products per term) and plain BF16.
 constexpr int kBf16BlockTarget = 768;
+constexpr int kBf16BlockTargetPlain = 384;
 // The batched contraction (throughput-bound, plenty of blocks) takes two
 // row tiles per wave: each staged B fragment then feeds twice the MFMAs.
 constexpr int kBatchBf16RowTiles = 2;
