@@ -1,5 +1,6 @@
 // Device-side helpers shared by the GN-MPPI kernels (gfx950, wave64).
 #pragma once
+#include <type_traits>
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -92,5 +93,15 @@ __device__ __forceinline__ float infinity<float>() {
 
 __device__ __forceinline__ float dsqrt(float v) { return __builtin_sqrtf(v); }
 __device__ __forceinline__ double dsqrt(double v) { return __builtin_sqrt(v); }
+
+// f(std::integral_constant<int, S>{}) for S = B .. E - 1, so that the body
+// sees its index as a constant expression.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
 
 }  // namespace gnm

@@ -501,9 +501,11 @@ __device__ __forceinline__ void contract_bf16_block(
     load_b(kbeg + kBf16Step, breg[1]);
     store_b(0, breg[0]);
     __syncthreads();
+    // step at k0; LOADS: fetch B two and A kBf16Depth steps ahead (every
+    // ring turn but the last), STORE: hand B of the next step to LDS
     auto step = [&](int k0, float (&as)[TM][8], BReg (&bnext)[PER_THREAD],
-                    BReg (&bstore)[PER_THREAD], int buf) {
-      load_b(k0 + 2 * kBf16Step, bnext);
+                    BReg (&bstore)[PER_THREAD], int buf, auto loads, auto store) {
+      if constexpr (decltype(loads)::value) load_b(k0 + 2 * kBf16Step, bnext);
       const int kl = k0 + 8 * kq;
       bf16x8 ah[TM], al[TM];
       if (k0 + kBf16Step <= kend) {  // uniform: a whole step inside the slice
@@ -527,7 +529,7 @@ __device__ __forceinline__ void contract_bf16_block(
               al[t][e] = static_cast<__bf16>(v - static_cast<float>(ah[t][e]));
           }
       }
-      load_a(k0 + D * kBf16Step, as);
+      if constexpr (decltype(loads)::value) load_a(k0 + D * kBf16Step, as);
 #pragma unroll
       for (int tn = 0; tn < NT; ++tn) {
         const bf16x8 bh = stage[buf][0][kq][16 * tn + r16];
@@ -546,14 +548,23 @@ __device__ __forceinline__ void contract_bf16_block(
           }
         }
       }
-      store_b(buf ^ 1, bstore);
+      if constexpr (decltype(store)::value) store_b(buf ^ 1, bstore);
       __syncthreads();
     };
-    for (int s = 0; s < nstep; s += D) {
+    // whole ring turns; the last one fetches nothing and stores only the B
+    // of its own steps
+    const int nturn = (nstep + D - 1) / D;
+    for (int s = 0; s < (nturn - 1) * D; s += D) {
 #pragma unroll
       for (int d = 0; d < D; ++d)
-        step(kbeg + (s + d) * kBf16Step, a[d], breg[d & 1], breg[(d + 1) & 1], d & 1);
+        step(kbeg + (s + d) * kBf16Step, a[d], breg[d & 1], breg[(d + 1) & 1], d & 1,
+             std::true_type{}, std::true_type{});
     }
+    static_for<0, D>([&](auto dc) {
+      constexpr int d = decltype(dc)::value;
+      step(kbeg + ((nturn - 1) * D + d) * kBf16Step, a[d], breg[d & 1], breg[(d + 1) & 1], d & 1,
+           std::false_type{}, std::integral_constant<bool, (d + 1 < D)>{});
+    });
   }
   float* out = part + static_cast<int64_t>(by) * arows * npad;
 #pragma unroll

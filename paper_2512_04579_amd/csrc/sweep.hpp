@@ -228,16 +228,6 @@ __host__ __device__ constexpr int sweep_slots(int w) {
   return s;
 }
 
-// f(std::integral_constant<int, S>{}) for S = B .. E - 1, so that the body
-// sees its index as a constant expression.
-template <int B, int E, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    static_for<B + 1, E>(f);
-  }
-}
-
 // acc += A B^T over one 16-wide k block, A = rows of pa, B = rows of pb (row
 // stride kSweepLd, k = column).  Step s takes k = 4 (l / 16) + s from lane l,
 // so each lane reads its 4 k-values as two 16-byte LDS loads.
