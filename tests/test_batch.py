@@ -24,7 +24,9 @@ from paper_2512_04579_amd.batch import BatchGNMPPI, autotune
 from paper_2512_04579_amd.problem import DeviceProblem
 from paper_2512_04579_amd.solver import GNMPPI
 
-SHAPES = [(3, 7, 64), (4, 12, 96), (5, 20, 128), (8, 9, 256), (9, 33, 384), (16, 16, 512)]
+# K = 100: a last k-step of 4 values (K % 32 == 4) in the batched contraction
+SHAPES = [(3, 7, 64), (4, 12, 96), (5, 20, 128), (6, 10, 100), (8, 9, 256), (9, 33, 384),
+          (16, 16, 512)]
 
 
 def _instances():
