@@ -167,8 +167,9 @@ def reference_c3(inst):
 
 def pick_schedule(dp, x0, st, seed: int, iters: int = 50) -> str:
     """The fastest iteration schedule (SCHEDULES in the solver module: the
-    direction without J on one stream, or J formed with G^{-1} on a side
-    stream in one of three orders) for this problem: a graph of ``iters``
+    direction without J on one stream, with or without the nominal residuals
+    handed over by the line search, or J formed with G^{-1} on a side stream
+    in one of three orders) for this problem: a graph of ``iters``
     captured iterations per schedule (the length of the timed graphs: "ahead"
     pays for its first iteration's side work once per graph), three replays
     each, the shortest replay counts."""
@@ -176,7 +177,7 @@ def pick_schedule(dp, x0, st, seed: int, iters: int = 50) -> str:
 
     from paper_2512_04579_amd.solver import make_solver
     best, pick = None, "direct"
-    for mode in ("direct", "ahead", "prefetch", "same"):
+    for mode in ("direct", "direct-line", "ahead", "prefetch", "same"):
         solver = make_solver(dp, x0, st, mode, seed=seed, max_iters=iters)
         graph = solver.capture(iters)
         graph.replay()
@@ -639,12 +640,14 @@ def main():
     ap.add_argument("--mppi-iters", type=int, default=1500)
     ap.add_argument("--graph-chunk", type=int, default=50, help="iterations per captured graph")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graphs")
-    ap.add_argument("--schedule", choices=("auto", "direct", "formed", "ahead", "prefetch", "same"),
+    ap.add_argument("--schedule", choices=("auto", "direct", "direct-line", "formed", "ahead",
+                                           "prefetch", "same"),
                     default="auto",
                     help="iteration schedule of the graphs: direct = the GGN direction without "
-                         "forming J, one stream; formed = J formed, one stream; ahead / prefetch "
+                         "forming J, one stream; direct-line = the same with the nominal residuals "
+                         "from the line search; formed = J formed, one stream; ahead / prefetch "
                          "/ same = J formed, G^{-1} on a side stream (auto: the fastest of "
-                         "direct, ahead, prefetch, same)")
+                         "direct, direct-line, ahead, prefetch, same)")
     ap.add_argument("--kernel-reps", type=int, default=50, help="rollout launches for the roofline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")

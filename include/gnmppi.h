@@ -295,6 +295,23 @@ int gnmppi_line_search(const gnmppi_problem *p, const void *x0, void *U,
                        const void *dU, const void *alpha, int32_t L, void *C,
                        double *info, int32_t *status, void *stream);
 
+/* gnmppi_line_search that also returns the nominal rollout of the updated
+ * controls, the r0 and c0 that the next iteration's rollout (Eqs. (1), (2),
+ * (4)) would produce for column K: the chosen candidate U + alpha[j*] dU IS
+ * the next iterate, so its residual rows (kept while the candidates roll out)
+ * and its cost are those values, and that rollout can leave out the nominal
+ * column.  Rc: device scratch for the L candidates' residual vectors, L * m
+ * entries of dtype, m = N (nx + nu); r0: m entries (out); c0: one entry
+ * (out, 1/2 ||r0||^2, summed in the line search's order).  If no candidate
+ * cost is finite, U, r0 and c0 are left unchanged.  The rows follow R's
+ * order; their values are bitwise those of the rollout for the same
+ * controls.  Null Rc, r0 or c0: GNMPPI_EINVAL.  Everything else as
+ * gnmppi_line_search. */
+int gnmppi_line_search_nominal(const gnmppi_problem *p, const void *x0, void *U,
+                               const void *dU, const void *alpha, int32_t L,
+                               void *C, double *info, int32_t *status, void *Rc,
+                               void *r0, void *c0, void *stream);
+
 /* ---- batched iterations ----------------------------------------------------
  *
  * Many independent chain MPC instances of uneven size solved together: one

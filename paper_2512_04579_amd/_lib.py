@@ -97,6 +97,9 @@ SIGNATURES = {
                                           c_int64, c_double, c_void_p, c_void_p, c_void_p]),
     "gnmppi_line_search": (c_int32, [PROBLEM_P, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
                                      c_void_p, c_void_p, c_void_p, c_void_p]),
+    "gnmppi_line_search_nominal": (c_int32, [PROBLEM_P, c_void_p, c_void_p, c_void_p, c_void_p,
+                                             c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                             c_void_p, c_void_p, c_void_p]),
     "gnmppi_batch_workspace": (c_size_t, [PROBLEM_P, c_int32, BATCH_P, BSET_P, BTUNE_P]),
     "gnmppi_batch_prepare": (c_int32, [PROBLEM_P, c_int32, BATCH_P, BSET_P, BTUNE_P, c_void_p, c_size_t]),
     "gnmppi_batch_iteration": (c_int32, [PROBLEM_P, c_int32, BATCH_P, BSET_P, BTUNE_P, c_void_p,
@@ -284,6 +287,15 @@ def gnmppi_line_search(problem, x0, U, dU, alpha, C=None, info=None, status=None
     _check("gnmppi_line_search", load().gnmppi_line_search(
         ctypes.byref(problem.c), _ptr(x0), _ptr(U), _ptr(dU), _ptr(alpha), alpha.numel(), _ptr(C),
         _ptr(info), _ptr(status), _stream(stream)))
+
+
+def gnmppi_line_search_nominal(problem, x0, U, dU, alpha, Rc, r0, c0, C=None, info=None,
+                               status=None, stream=None):
+    """gnmppi_line_search that also writes r0, c0 of the updated controls;
+    Rc: scratch of alpha.numel() * r0.numel() entries."""
+    _check("gnmppi_line_search_nominal", load().gnmppi_line_search_nominal(
+        ctypes.byref(problem.c), _ptr(x0), _ptr(U), _ptr(dU), _ptr(alpha), alpha.numel(), _ptr(C),
+        _ptr(info), _ptr(status), _ptr(Rc), _ptr(r0), _ptr(c0), _stream(stream)))
 
 
 def gnmppi_batch_workspace(shared, count, inst, settings, tuning) -> int:

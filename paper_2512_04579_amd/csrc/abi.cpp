@@ -225,6 +225,17 @@ int gnmppi_line_search(const gnmppi_problem* p, const void* x0, void* U, const v
       gnm::launch_line_search(*p, x0, U, dU, alpha, L, C, info, status, as_stream(stream)));
 }
 
+int gnmppi_line_search_nominal(const gnmppi_problem* p, const void* x0, void* U, const void* dU,
+                               const void* alpha, int32_t L, void* C, double* info,
+                               int32_t* status, void* Rc, void* r0, void* c0, void* stream) {
+  if (!problem_ok(p) || !sizes_fit(p) || x0 == nullptr || U == nullptr || dU == nullptr ||
+      alpha == nullptr || Rc == nullptr || r0 == nullptr || c0 == nullptr)
+    return GNMPPI_EINVAL;
+  if (L < 1 || L > 64) return GNMPPI_EINVAL;
+  return status_of(gnm::launch_line_search(*p, x0, U, dU, alpha, L, C, info, status,
+                                           as_stream(stream), Rc, r0, c0));
+}
+
 int64_t gnmppi_mlp_param_count(int32_t n_in, int32_t n_hidden, int32_t n_out) {
   if (n_in < 1 || n_hidden < 1 || n_out < 1 || n_in > 4096 || n_hidden > 4096 || n_out > 4096)
     return 0;
@@ -284,6 +295,6 @@ const char* gnmppi_status_string(int32_t status) {
   }
 }
 
-int32_t gnmppi_abi_version(void) { return 3; }
+int32_t gnmppi_abi_version(void) { return 4; }
 
 }  // extern "C"

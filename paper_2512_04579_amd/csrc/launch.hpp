@@ -25,9 +25,12 @@ hipError_t launch_sample_rollout(const gnmppi_problem& p, const void* x0, const 
                                  double sigma, uint64_t seed, uint64_t stream_id, int antithetic,
                                  void* W, int64_t ldw, int K, void* R, int64_t ldr, void* C,
                                  void* r0, void* c0, hipStream_t st);
+// With Rc (L residual vectors of m = N (nx + nu) entries each): r0, c0 <- the
+// residuals and cost of the chosen candidate.
 hipError_t launch_line_search(const gnmppi_problem& p, const void* x0, void* U,
                               const void* dU, const void* alpha, int L, void* C,
-                              double* info, int32_t* status, hipStream_t st);
+                              double* info, int32_t* status, hipStream_t st,
+                              void* Rc = nullptr, void* r0 = nullptr, void* c0 = nullptr);
 
 hipError_t launch_mppi_update(int dtype, int n, int K, const void* C, const void* W,
                               int64_t ldw, double temperature, void* U, void* weights,

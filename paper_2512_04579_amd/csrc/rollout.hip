@@ -151,6 +151,29 @@ struct NoSink {
   __device__ __forceinline__ void step(int, int, bool, bool, T, T, T, T, T, T) {}
 };
 
+// One sample's residual rows as a contiguous vector (row k (4M + 2) + ... of
+// step k, the row order of R); rc == nullptr stores nothing.
+template <typename T>
+struct VectorSink {
+  T* rc;
+  int M;
+  __device__ __forceinline__ void step(int k, int i, bool has_mass, bool first, T e0, T e1, T e2,
+                                       T e3, T f0, T f1) {
+    if (rc == nullptr) return;
+    T* t = rc + k * (4 * M + 2);
+    if (has_mass) {
+      t[2 * i] = e0;
+      t[2 * i + 1] = e1;
+      t[2 * M + 2 * i] = e2;
+      t[2 * M + 2 * i + 1] = e3;
+    }
+    if (first) {
+      t[4 * M] = f0;
+      t[4 * M + 1] = f1;
+    }
+  }
+};
+
 // Stores the first nfr rows of one residual tile t (rows base .. base + nfr
 // of R, the columns col0 .. col0 + kSpb of the block) as contiguous row
 // segments of the sample-fastest R (or into r0 for the nominal column K),
@@ -715,17 +738,53 @@ __device__ __forceinline__ void line_select_and_apply(T* costs, int L, int n, T*
   }
 }
 
+// With Rc (the candidates' residual vectors, m apart): r0 <- the residuals of
+// the chosen candidate and c0 <- its cost, i.e. the nominal residuals and cost
+// of the updated controls (left as they are when no candidate is finite: U is
+// unchanged then).  After line_select_and_apply, whose barrier orders the
+// candidates' stores before these reads.
+template <typename T>
+__device__ __forceinline__ void line_nominal_out(const T* costs, int jstar, const T* Rc, int64_t m,
+                                                 T* __restrict__ r0, T* __restrict__ c0) {
+  if (Rc == nullptr || jstar < 0) return;  // uniform
+  const T* src = Rc + jstar * m;
+  // kBatch loads in flight per thread (clamped into the vector) before their
+  // stores: one memory round trip per batch instead of one per element
+  constexpr int kBatch = 16;
+  const int64_t nt = blockDim.x;
+  for (int64_t t0 = threadIdx.x; t0 < m; t0 += kBatch * nt) {
+    T v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) v[u] = src[min(t0 + u * nt, m - 1)];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (t0 + u * nt < m) r0[t0 + u * nt] = v[u];
+  }
+  if (threadIdx.x == 0) c0[0] = costs[jstar];
+}
+
+// With Rc, candidate j's residual rows go to Rc + j m and the chosen one's
+// become r0 (line_nominal_out).
 template <typename T, int G>
 __device__ __forceinline__ void line_search_chain_block(
     ChainDev<T> cd, int N, const T* __restrict__ x0, const T* __restrict__ q,
     const T* __restrict__ r, const T* __restrict__ xref, T* U, const T* __restrict__ dU,
     const T* __restrict__ alpha, int L, T* __restrict__ Cout, double* info, int32_t* status,
-    int stage_ctl, unsigned char* ctl_raw) {
+    int stage_ctl, unsigned char* ctl_raw, T* __restrict__ Rc = nullptr,
+    T* __restrict__ r0 = nullptr, T* __restrict__ c0 = nullptr) {
   __shared__ T costs[64];
   __shared__ int jstar;
   const int j = threadIdx.x / G;
   const int jj = j < L ? j : L - 1;
   const int n = 2 * N;
+  const int64_t m = static_cast<int64_t>(N) * (4 * cd.M + 2);
+  // groups past the last candidate repeat it and store nothing
+  VectorSink<T> vsink{Rc != nullptr && j < L ? Rc + j * m : nullptr, cd.M};
+  auto roll = [&](const auto& ctrl) {
+    if (Rc != nullptr) return chain_rollout<T, G, true>(cd, N, x0, q, r, xref, ctrl, vsink);
+    NoSink sink;
+    return chain_rollout<T, G, true>(cd, N, x0, q, r, xref, ctrl, sink);
+  };
   T c;
   if (stage_ctl) {
     T* Us = reinterpret_cast<T*>(ctl_raw);
@@ -735,16 +794,13 @@ __device__ __forceinline__ void line_search_chain_block(
       dUs[e] = dU[e];
     }
     __syncthreads();
-    CtrlLineStaged<T> ctrl{Us, dUs, alpha[jj]};
-    NoSink sink;
-    c = chain_rollout<T, G, true>(cd, N, x0, q, r, xref, ctrl, sink);
+    c = roll(CtrlLineStaged<T>{Us, dUs, alpha[jj]});
   } else {
-    CtrlLine<T> ctrl{U, dU, alpha[jj]};
-    NoSink sink;
-    c = chain_rollout<T, G, true>(cd, N, x0, q, r, xref, ctrl, sink);
+    c = roll(CtrlLine<T>{U, dU, alpha[jj]});
   }
   if (j < L && (threadIdx.x & (G - 1)) == 0) costs[j] = c;
   line_select_and_apply(costs, L, n, U, dU, alpha, Cout, info, status, &jstar);
+  line_nominal_out(costs, jstar, Rc, m, r0, c0);
 }
 
 template <typename T, int G>
@@ -752,10 +808,10 @@ __global__ void __launch_bounds__(1024) line_search_chain_kernel(
     ChainDev<T> cd, int N, const T* __restrict__ x0, const T* __restrict__ q,
     const T* __restrict__ r, const T* __restrict__ xref, T* U, const T* __restrict__ dU,
     const T* __restrict__ alpha, int L, T* __restrict__ Cout, double* info, int32_t* status,
-    int stage_ctl) {
+    int stage_ctl, T* __restrict__ Rc, T* __restrict__ r0, T* __restrict__ c0) {
   extern __shared__ unsigned char ctl_raw[];
   line_search_chain_block<T, G>(cd, N, x0, q, r, xref, U, dU, alpha, L, Cout, info, status,
-                                stage_ctl, ctl_raw);
+                                stage_ctl, ctl_raw, Rc, r0, c0);
 }
 
 // Batched: item = instance; L * G threads.
@@ -778,15 +834,20 @@ template <typename T, int D>
 __global__ void __launch_bounds__(64) line_search_di_kernel(
     int N, T dt, const T* __restrict__ x0, const T* __restrict__ q, const T* __restrict__ r,
     const T* __restrict__ xref, T* U, const T* __restrict__ dU, const T* __restrict__ alpha,
-    int L, T* __restrict__ Cout, double* info, int32_t* status) {
+    int L, T* __restrict__ Cout, double* info, int32_t* status, T* __restrict__ Rc,
+    T* __restrict__ r0, T* __restrict__ c0) {
   __shared__ T costs[64];
   __shared__ int jstar;
   const int j = threadIdx.x;
+  const int64_t m = static_cast<int64_t>(N) * 3 * D;
   if (j < L) {
     CtrlLine<T> ctrl{U, dU, alpha[j]};
-    costs[j] = di_rollout<T, D, false>(N, dt, x0, q, r, xref, ctrl, nullptr, 0, 0, false);
+    costs[j] = Rc != nullptr
+                   ? di_rollout<T, D, true>(N, dt, x0, q, r, xref, ctrl, Rc + j * m, 1, 0, true)
+                   : di_rollout<T, D, false>(N, dt, x0, q, r, xref, ctrl, nullptr, 0, 0, false);
   }
   line_select_and_apply(costs, L, N * D, U, dU, alpha, Cout, info, status, &jstar);
+  line_nominal_out(costs, jstar, Rc, m, r0, c0);
 }
 
 // ---- dispatch ---------------------------------------------------------------
@@ -883,7 +944,7 @@ hipError_t rollout_typed(const gnmppi_problem& p, const T* x0, const T* U, const
 template <typename T>
 hipError_t line_search_typed(const gnmppi_problem& p, const T* x0, T* U, const T* dU,
                              const T* alpha, int L, T* C, double* info, int32_t* status,
-                             hipStream_t st) {
+                             hipStream_t st, T* Rc, T* r0, T* c0) {
   const T* q = static_cast<const T*>(p.q);
   const T* r = static_cast<const T*>(p.r);
   const T* xr = static_cast<const T*>(p.x_ref);
@@ -897,7 +958,7 @@ hipError_t line_search_typed(const gnmppi_problem& p, const T* x0, T* U, const T
 #define GNM_LS_CASE(GG)                                                                          \
   case GG:                                                                                       \
     hipLaunchKernelGGL((line_search_chain_kernel<T, GG>), dim3(1), dim3(threads), lds, st, cd,    \
-                       p.N, x0, q, r, xr, U, dU, alpha, L, C, info, status, stage);              \
+                       p.N, x0, q, r, xr, U, dU, alpha, L, C, info, status, stage, Rc, r0, c0);  \
     break;
     switch (G) {
       GNM_LS_CASE(1)
@@ -914,7 +975,7 @@ hipError_t line_search_typed(const gnmppi_problem& p, const T* x0, T* U, const T
 #define GNM_LSD_CASE(DD)                                                                      \
   case DD:                                                                                    \
     hipLaunchKernelGGL((line_search_di_kernel<T, DD>), dim3(1), dim3(64), 0, st, p.N, dt, x0, q, \
-                       r, xr, U, dU, alpha, L, C, info, status);                              \
+                       r, xr, U, dU, alpha, L, C, info, status, Rc, r0, c0);                  \
     break;
     switch (p.nu) {
       GNM_LSD_CASE(1)
@@ -1057,16 +1118,18 @@ hipError_t launch_batch_line_search(int G, const BatchInst* inst, const BatchLau
 
 hipError_t launch_line_search(const gnmppi_problem& p, const void* x0, void* U, const void* dU,
                               const void* alpha, int L, void* C, double* info, int32_t* status,
-                              hipStream_t st) {
+                              hipStream_t st, void* Rc, void* r0, void* c0) {
   if (p.dtype == GNMPPI_F32)
     return line_search_typed<float>(p, static_cast<const float*>(x0), static_cast<float*>(U),
                                     static_cast<const float*>(dU),
                                     static_cast<const float*>(alpha), L, static_cast<float*>(C),
-                                    info, status, st);
+                                    info, status, st, static_cast<float*>(Rc),
+                                    static_cast<float*>(r0), static_cast<float*>(c0));
   return line_search_typed<double>(p, static_cast<const double*>(x0), static_cast<double*>(U),
                                    static_cast<const double*>(dU),
                                    static_cast<const double*>(alpha), L, static_cast<double*>(C),
-                                   info, status, st);
+                                   info, status, st, static_cast<double*>(Rc),
+                                   static_cast<double*>(r0), static_cast<double*>(c0));
 }
 
 }  // namespace gnm

@@ -71,7 +71,7 @@ class GNMPPI:
 
     def __init__(self, dprob: DeviceProblem, x0, settings, seed: int = 1, U0=None,
                  sampler: str = "gaussian", max_iters: int | None = None, overlap=False,
-                 form_jacobian: bool = False):
+                 form_jacobian: bool = False, nominal_from_line: bool = False):
         self.p = dprob
         # form_jacobian: GetJacobian then the GGN step as two calls
         # (gnmppi_reconstruct_jacobian, gnmppi_ggn_step), J formed in HBM;
@@ -124,6 +124,17 @@ class GNMPPI:
         self.alpha = torch.tensor([settings.gamma ** j for j in range(settings.n_alpha)],
                                   dtype=dt, device=dev)
         self.C_line = torch.zeros(settings.n_alpha, dtype=dt, device=dev)
+        # nominal_from_line: the single-stream sampling path takes the nominal
+        # residuals of the next iterate from the line search (its chosen
+        # candidate is that iterate) instead of a nominal column in the next
+        # rollout: one block less for the rollout, residual stores and a copy
+        # more for the line search, which pays where the nominal column alone
+        # would take a CU's second or third block (bench.py times both).
+        # R_cand: scratch for the candidates' residual vectors
+        self.nominal_from_line = (nominal_from_line and not self.form_jacobian
+                                  and sampler == "gaussian")
+        self.R_cand = (torch.zeros(settings.n_alpha * m, dtype=dt, device=dev)
+                       if self.nominal_from_line else None)
         iters = max_iters if max_iters is not None else settings.iters
         self.info = torch.zeros(max(iters, 1), 3, dtype=torch.float64, device=dev)
         # status words per iteration: Jacobian (rank of G), GGN step (positive
@@ -183,13 +194,19 @@ class GNMPPI:
             _lib.gnmppi_perturbation_gram(W2, self.works[it % 2], self.m, self.status[it, 2:3], K)
         self._gram_for = it
 
-    def step(self, it: int, marks=None, ahead: bool = True):
+    def step(self, it: int, marks=None, ahead: bool = True, nominal: bool = True,
+             keep_nominal: bool = False):
         """One iteration of Alg. 1: GetJacobian, full GGN step, line search,
         apply; the covariance shrink enters through ``sigma(it)``.  With
         ``marks`` (a dict name -> list), a pair of timing events is recorded
         around each library call on the current stream.  With overlap
         "ahead" and ``ahead``, the side stream's work for iteration it + 1 is
-        enqueued once J of this iteration no longer needs the side stream."""
+        enqueued once J of this iteration no longer needs the side stream.
+        On the single-stream sampling path (``nominal_from_line``):
+        ``keep_nominal`` has the line search write r0, c0 of the updated
+        controls, and ``nominal=False`` rolls out without the nominal column,
+        taking r0 from the previous step's line search -- for consecutive
+        steps with no change of U in between."""
         K, sig = self.K, self.sigma(it)
         W = self.W[:, :K]
         work = self.works[it % 2] if self.ahead else self.work_j
@@ -200,9 +217,10 @@ class GNMPPI:
             # one launch draws W and rolls out (residuals and the nominal
             # cost only: the step never reads C)
             tick.start("sample_rollout")
+            skip = self.nominal_from_line and not nominal
             _lib.gnmppi_sample_rollout(self.p, self.x0, self.U, W, self.sigma(it), self.seed, it, K,
-                                       antithetic=self.s.antithetic, R=self.R[:, :K], r0=self.r0,
-                                       c0=self.c0)
+                                       antithetic=self.s.antithetic, R=self.R[:, :K],
+                                       r0=None if skip else self.r0, c0=None if skip else self.c0)
         else:
             tick.start("sample")
             if self.prefetch:
@@ -257,8 +275,13 @@ class GNMPPI:
             _lib.gnmppi_ggn_step(self.J, self.r0, self.s.lm_lambda, self.dU, self.work_g,
                                  self.status[it, 1:2])
         tick.next("line_search")
-        _lib.gnmppi_line_search(self.p, self.x0, self.U, self.dU, self.alpha, self.C_line,
-                                self.info[it], self.status[it, 3:4])
+        if self.nominal_from_line and keep_nominal:
+            _lib.gnmppi_line_search_nominal(self.p, self.x0, self.U, self.dU, self.alpha,
+                                            self.R_cand, self.r0, self.c0, self.C_line,
+                                            self.info[it], self.status[it, 3:4])
+        else:
+            _lib.gnmppi_line_search(self.p, self.x0, self.U, self.dU, self.alpha, self.C_line,
+                                    self.info[it], self.status[it, 3:4])
         tick.stop()
         if self.overlap and j_done is not None:
             self._side_gram(it + 1, after=j_done)
@@ -287,9 +310,13 @@ class GNMPPI:
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
             # the first iteration enqueues its own side-stream work; the last
-            # enqueues none, so every fork is joined inside the graph
+            # enqueues none, so every fork is joined inside the graph.  Only
+            # the first rolls out the nominal column (U may have changed
+            # between replays); each later one takes r0 from the line search
+            # before it
             for it in range(it0, it0 + iters):
-                self.step(it, ahead=it + 1 < it0 + iters)
+                self.step(it, ahead=it + 1 < it0 + iters, nominal=it == it0,
+                          keep_nominal=it + 1 < it0 + iters)
         self._gram_for = None
         return graph
 
@@ -302,7 +329,7 @@ class GNMPPI:
             e0.record()
             evs.append(e0)
         for it in range(iters):
-            self.step(it, ahead=it + 1 < iters)
+            self.step(it, ahead=it + 1 < iters, nominal=it == 0, keep_nominal=it + 1 < iters)
             if events:
                 e = torch.cuda.Event(enable_timing=True)
                 e.record()
@@ -315,17 +342,23 @@ class GNMPPI:
 
 
 # Iteration schedules of GNMPPI: "direct" -- one gnmppi_ggn_direction call per
-# iteration (J not formed), one stream; "formed" -- J formed
-# (gnmppi_reconstruct_jacobian, then gnmppi_ggn_step), one stream; "ahead",
-# "prefetch", "same" -- J formed, with G^{-1} factored on a side stream.
-SCHEDULES = {"direct": (False, False), "formed": (True, False), "ahead": (True, "ahead"),
-             "prefetch": (True, "prefetch"), "same": (True, "same")}
+# iteration (J not formed), one stream; "direct-line" -- the same, and in a
+# run of steps the line search hands the next step its nominal residuals
+# (gnmppi_line_search_nominal) so that rollout leaves out the nominal column;
+# "formed" -- J formed (gnmppi_reconstruct_jacobian, then gnmppi_ggn_step),
+# one stream; "ahead", "prefetch", "same" -- J formed, with G^{-1} factored on
+# a side stream.  Values: (form J, side-stream mode, nominal from the line
+# search).
+SCHEDULES = {"direct": (False, False, False), "direct-line": (False, False, True),
+             "formed": (True, False, False), "ahead": (True, "ahead", False),
+             "prefetch": (True, "prefetch", False), "same": (True, "same", False)}
 
 
 def make_solver(dprob: DeviceProblem, x0, settings, schedule: str = "direct", **kw) -> GNMPPI:
     """GNMPPI with the iteration schedule ``schedule`` (a key of SCHEDULES)."""
-    form, overlap = SCHEDULES[schedule]
-    return GNMPPI(dprob, x0, settings, overlap=overlap, form_jacobian=form, **kw)
+    form, overlap, line_nominal = SCHEDULES[schedule]
+    return GNMPPI(dprob, x0, settings, overlap=overlap, form_jacobian=form,
+                  nominal_from_line=line_nominal, **kw)
 
 
 class PlainMPPI:

@@ -151,7 +151,7 @@ def test_other_entry_points_reject_bad_arguments():
 def test_status_strings_and_version():
     assert _lib.status_string(_lib.ENOTPD) == "normal matrix not positive definite"
     assert _lib.status_string(123) == "unknown status"
-    assert _lib.gnmppi_abi_version() == 3
+    assert _lib.gnmppi_abi_version() == 4
 
 
 def test_mlp_entry_points_reject_bad_arguments():
@@ -187,6 +187,22 @@ def test_sample_rollout_rejects_bad_arguments():
     assert call(sigma=float("nan")) == _lib.EINVAL
     assert call(R=None, C=None) == _lib.EINVAL  # nothing wanted of the K columns
     assert call(r0=0x50, c0=None) == _lib.EINVAL
+
+
+def test_line_search_nominal_rejects_bad_arguments():
+    lib = _lib.load()
+    p = _problem()
+
+    def call(L=16, Rc=0x50, r0=0x60, c0=0x70, U=0x20):
+        return lib.gnmppi_line_search_nominal(ctypes.byref(p), 0x10, U, 0x30, 0x40, L, None, None,
+                                              None, Rc, r0, c0, None)
+
+    assert call(Rc=None) == _lib.EINVAL   # the candidates' residuals have nowhere to go
+    assert call(r0=None) == _lib.EINVAL
+    assert call(c0=None) == _lib.EINVAL
+    assert call(U=None) == _lib.EINVAL
+    assert call(L=0) == _lib.EINVAL
+    assert call(L=65) == _lib.EINVAL
 
 
 def test_ggn_direction_rejects_bad_arguments():

@@ -751,6 +751,76 @@ def test_line_search_with_no_finite_candidate_reports_it(n_masses):
     assert int(st.item()) == _lib.ENONFINITE
 
 
+@pytest.mark.parametrize("case", ["c2", "c1", "chain5_f64", "chain12_f32_L33"])
+def test_line_search_nominal_returns_the_next_nominal_rollout(case):
+    # r0, c0 of gnmppi_line_search_nominal are the nominal rollout of the
+    # updated controls: r0 bitwise equal to the rollout's column K (the same
+    # kernels' arithmetic on the same controls), c0 = 1/2 ||r0||^2 up to the
+    # order of the sum; U, C and info as from gnmppi_line_search
+    L = 16
+    if case == "c2":
+        w = wl.c2()
+        prob, x0, dtype = w.problem, w.x0, "f32"
+    elif case == "c1":
+        w = wl.c1()
+        prob, x0, dtype = w.problem, w.x0, "f64"
+    elif case == "chain5_f64":
+        prob, x0 = wl.chain_problem(n_masses=5, N=11, seed=9)
+        dtype = "f64"
+    else:
+        prob, x0 = wl.chain_problem(n_masses=12, N=9, seed=4)
+        dtype, L = "f32", 33  # groups of 16 lanes past the last candidate
+    rng = np.random.default_rng(7)
+    U = rnd(0.1 * rng.standard_normal(prob.n), dtype)
+    d = rnd(0.5 * rng.standard_normal(prob.n), dtype)
+    alphas = to_dev(rnd(0.5 ** np.arange(L), dtype), dtype)
+    dp = DeviceProblem(prob, dtype)
+    x0d, dd = to_dev(rnd(x0, dtype), dtype), to_dev(d, dtype)
+    m = prob.m
+    outs = []
+    for nominal in (False, True):
+        Ud = to_dev(U, dtype)
+        Cd = to_dev(np.zeros(L), dtype)
+        info = torch.zeros(3, dtype=torch.float64, device=device())
+        st = torch.full((1,), 99, dtype=torch.int32, device=device())
+        if nominal:
+            Rc = to_dev(np.full(L * m, np.nan), dtype)
+            r0 = to_dev(np.full(m, np.nan), dtype)
+            c0 = to_dev(np.full(1, np.nan), dtype)
+            _lib.gnmppi_line_search_nominal(dp, x0d, Ud, dd, alphas, Rc, r0, c0, Cd, info, st)
+        else:
+            _lib.gnmppi_line_search(dp, x0d, Ud, dd, alphas, Cd, info, st)
+        _sync()
+        outs.append((host(Ud), host(Cd), host(info), int(st.item())))
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)
+    # the nominal rollout of the updated controls
+    r0_ref = to_dev(np.zeros(m), dtype)
+    c0_ref = to_dev(np.zeros(1), dtype)
+    _lib.gnmppi_rollout(dp, x0d, Ud, None, 0, None, None, r0_ref, c0_ref)
+    _sync()
+    np.testing.assert_array_equal(host(r0), host(r0_ref))
+    assert_parity(host(c0), host(c0_ref), dtype, "c0")
+
+
+def test_line_search_nominal_keeps_r0_when_no_candidate_is_finite():
+    prob, x0 = wl.chain_problem(n_masses=4, N=6, seed=1)
+    dp = DeviceProblem(prob, "f32")
+    alphas = to_dev(np.array([1.0, 0.5, 0.25]), "f32")
+    U0 = rnd(0.1 * np.random.default_rng(2).standard_normal(prob.n), "f32")
+    Ud = to_dev(U0, "f32")
+    Rc = to_dev(np.zeros(3 * prob.m), "f32")
+    r0 = to_dev(np.full(prob.m, 7.0), "f32")
+    c0 = to_dev(np.full(1, 7.0), "f32")
+    st = torch.zeros(1, dtype=torch.int32, device=device())
+    _lib.gnmppi_line_search_nominal(dp, to_dev(x0, "f32"), Ud, to_dev(np.full(prob.n, 1e30), "f32"),
+                                    alphas, Rc, r0, c0, None, None, st)
+    _sync()
+    assert int(st.item()) == _lib.ENONFINITE
+    np.testing.assert_array_equal(host(Ud), U0)
+    assert (host(r0) == 7.0).all() and host(c0)[0] == 7.0
+
+
 @pytest.mark.parametrize("M", [3, 4, 5, 8])
 def test_rollout_diverging_sample_leaves_its_neighbours_intact(M):
     # With fewer than 16 lanes per sample, two or four samples share a 16-lane
