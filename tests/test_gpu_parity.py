@@ -888,6 +888,24 @@ def test_c2_first_iteration_matches_oracle():
     assert costs[0] < ocp.cost(rp, rnd(w.x0, "f32"), np.zeros(p.n))
 
 
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_nominal_from_the_line_search_keeps_the_trajectory(name):
+    # direct-line rolls out without the nominal column after the first step
+    # and takes r0 from the line search before it: the same iterates, bit
+    # for bit, as direct (r0 is bitwise the rollout's column K)
+    w = wl.get(name)
+    dp = DeviceProblem(w.problem, w.dtype)
+    out = []
+    for schedule in ("direct", "direct-line"):
+        solver = _solver(dp, w, schedule, seed=9, max_iters=4)
+        solver.solve(4)
+        _sync()
+        out.append((host(solver.U), host(solver.info), host(solver.r0)))
+        assert (solver.history(4)[2] == 0).all()
+    for a, b in zip(out[0], out[1]):
+        np.testing.assert_array_equal(a, b)
+
+
 @pytest.mark.parametrize("schedule", list(SCHEDULES))
 def test_c1_solver_with_and_without_stream_overlap(schedule):
     w = wl.c1()
