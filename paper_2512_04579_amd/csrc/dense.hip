@@ -389,15 +389,18 @@ static void split_plan(int rows, int K, int step, int kw, int& nsplit_out, int& 
   split_len_out = steps_per_split * step;
 }
 
-// k-split of the BF16 contraction: blocks of 64 kBf16RowTiles rows; aim at
-// kBf16BlockTarget blocks (terms = 3) or kBf16BlockTargetPlain (terms = 1,
-// a third of the MFMA work per step: fewer, longer blocks stream R better and
-// write fewer partials) with at least four k-steps per block, and a whole
-// number of turns of the kernel's load ring per slice.  The plain target is
-// the smaller one, so terms = 3 gives the larger split count.
+// k-split of the BF16 contraction: blocks of 64 bf16_row_tiles(terms) rows;
+// aim at kBf16BlockTarget blocks (terms = 3) or kBf16BlockTargetPlain
+// (terms = 1, a third of the MFMA work per step: fewer, longer blocks stream
+// R better and write fewer partials) with at least four k-steps per block,
+// and a whole number of turns of the kernel's load ring per slice.  The plain
+// plan's 64-row k-slices are no more than the BF16x3 plan's, so terms = 3
+// gives the larger split count.
 static void bf16_split_plan(int m, int K, int terms, int& nsplit_out, int& split_len_out) {
-  static_assert(kBf16BlockTargetPlain <= kBf16BlockTarget, "workspace sized for terms = 3");
-  const int row_blocks = (m + 64 * kBf16RowTiles - 1) / (64 * kBf16RowTiles);
+  static_assert(kBf16BlockTargetPlain * kBf16RowTilesPlain <= kBf16BlockTarget * kBf16RowTiles,
+                "workspace sized for terms = 3");
+  const int rt = bf16_row_tiles(terms);
+  const int row_blocks = (m + 64 * rt - 1) / (64 * rt);
   const int ksteps = (K + 31) / 32;
   const int target = terms == 3 ? kBf16BlockTarget : kBf16BlockTargetPlain;
   int nsplit = (target + row_blocks - 1) / row_blocks;

@@ -608,7 +608,8 @@ hipError_t bf16_dispatch(int nt, dim3 grid, hipStream_t st, int m, int n, int K,
                          int split_len, float* part, int npad, int arows) {
 #define GNM_BF_CASE(NT)                                                                        \
   case NT:                                                                                     \
-    hipLaunchKernelGGL((contract_bf16_kernel<TERMS, NT, kBf16RowTiles, VEC>), grid, dim3(256), 0, \
+    hipLaunchKernelGGL((contract_bf16_kernel<TERMS, NT, bf16_row_tiles(TERMS), VEC>), grid,      \
+                       dim3(256), 0,                                                              \
                        st, m, n, K, R, ldr, r0, W, ldw, split_len, part, npad, arows);         \
     break;
   switch (nt) {
@@ -688,7 +689,8 @@ hipError_t launch_contract_bf16(int terms, int m, int n, int K, const float* R, 
                                 int split_len, float* part, int npad, hipStream_t st,
                                 bool with_gram) {
   const int arows = with_gram ? m + n : m;
-  dim3 grid((arows + 64 * kBf16RowTiles - 1) / (64 * kBf16RowTiles), nsplit);
+  const int rt = bf16_row_tiles(terms);
+  dim3 grid((arows + 64 * rt - 1) / (64 * rt), nsplit);
   const int nt = (n + 15) / 16;
   // 16-byte loads of whole 8-value groups: aligned rows of R and W, and K % 8
   // == 0 so that no group runs past the end of a row

@@ -64,15 +64,20 @@ struct ContractArgs {
 // split its k-steps between them (the planner sizes k-splits with it).
 int contract_kw(size_t elem_size, int ncol);
 // launch_contract_bf16: 16-row MFMA tiles per wave (a block covers 64 times
-// as many rows) and the planner's target for its blocks per k-slice.
+// as many rows) and the planner's target for its blocks per k-slice, for
+// BF16x3 (three products per term) and for plain BF16 (one product: each
+// staged B fragment then feeds two row tiles, and fewer, longer blocks
+// stream R better).
 constexpr int kBf16RowTiles = 1;
+constexpr int kBf16RowTilesPlain = 2;
+constexpr int bf16_row_tiles(int terms) { return terms == 3 ? kBf16RowTiles : kBf16RowTilesPlain; }
 // k-steps that the BF16 contraction's A loads run ahead of their use (an
 // even number: the loop turns over the A ring and both B buffers together).
 constexpr int kBf16Depth = 2;
 // Blocks the planner aims at for one BF16 contraction (row blocks x k-slices):
-// BF16x3 (three products per term) and plain BF16.
+// BF16x3 and plain BF16.
 constexpr int kBf16BlockTarget = 768;
-constexpr int kBf16BlockTargetPlain = 384;
+constexpr int kBf16BlockTargetPlain = 192;
 // The batched contraction (throughput-bound, plenty of blocks) takes two
 // row tiles per wave: each staged B fragment then feeds twice the MFMAs.
 constexpr int kBatchBf16RowTiles = 2;
