@@ -5,13 +5,13 @@
 //      symmetric matrix (lower triangle) into a full symmetric double matrix,
 //      one block per row so that every partial load is in flight at once.
 //  * sweep_kernel<R> (sweep.hpp, instantiated in the sweep_*.hip units) --
-//      one workgroup of 4 waves sweeps an SPD matrix with
+//      one workgroup of 8 waves sweeps an SPD matrix with
 //      the symmetric sweep operator (Gauss-Jordan elimination without
 //      pivoting; for an SPD matrix its pivots are the Cholesky pivots
 //      squared).  The lower triangle lives in registers as 16 x 16 tiles of
-//      the f64 MFMA accumulator layout, whole tile rows per wave 1..3.
+//      the f64 MFMA accumulator layout, whole tile rows per wave 1..7.
 //      Pivots go in blocks of 16: wave 0 sweeps each diagonal block in
-//      registers (two pivots per step), waves 1..3 apply the rank-16 update
+//      registers (two pivots per step), waves 1..7 apply the rank-16 update
 //      of the previous block on the MFMA meanwhile -- one barrier per block.
 //      Sweeping pivots 0..n-1 of [[H, g], [g^T, c]] leaves -H^{-1} in the
 //      leading block and H^{-1} g in the last row: the same kernel yields

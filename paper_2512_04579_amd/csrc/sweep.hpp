@@ -159,7 +159,8 @@ __device__ __forceinline__ void diag_pivots(double (&d4)[4], int nbv, double tol
 
 // The matrix lives in registers as 16 x 16 tiles (r, c), c <= r, of the
 // lower triangle in the f64 MFMA accumulator layout (element e of lane l is
-// (16 r + 4 e + l / 16, 16 c + l % 16)); waves 1..3 own whole tile rows.
+// (16 r + 4 e + l / 16, 16 c + l % 16)); waves 1 .. kSweepWaves - 1 own whole
+// tile rows.
 // With B the pivots of block b, D = A_BB and Z = A_{:,B} with its rows in B
 // replaced by -I, sweeping B is A <- A_{\B} - Y Z^T with Y = Z D^{-1}, where
 // A_{\B} has the rows and columns in B zeroed; the columns in B then hold Y
@@ -169,7 +170,7 @@ __device__ __forceinline__ void diag_pivots(double (&d4)[4], int nbv, double tol
 //    owner), applies block b - 1 to it, sweeps its pivots in registers and
 //    publishes D^{-1}, the tile's Y rows, its -I panel rows and the swept
 //    tile;
-//  * waves 1..3 apply block a = t - 2 to their tiles (each forms Y for its
+//  * the update waves apply block a = t - 2 to their tiles (each forms Y for its
 //    own rows on the MFMA), write the panel column of block t - 1 and hand
 //    diagonal tile (t, t) to wave 0.
 // So the pivot latency chain of one block overlaps the rank-16 update of the
@@ -177,7 +178,8 @@ __device__ __forceinline__ void diag_pivots(double (&d4)[4], int nbv, double tol
 // solve_only: only the augmented row npiv is wanted (the GGN direction), so
 // tiles whose rows are all pivoted -- the part of the inverse that no later
 // pivot reads -- are not updated and their Y is not formed.
-constexpr int kSweepWaves = 4;
+constexpr int kSweepWaves = 8;
+constexpr int kSweepThreads = kSweepWaves * kWave;
 
 // Orders LDS traffic between the lanes of one wave (a wave executes its LDS
 // operations in order, so no s_barrier is needed).
@@ -187,13 +189,13 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Tile rows -> update waves 1..3: greedy, largest row (r + 1 tiles) first, to
-// the least loaded wave.
+// Tile rows -> update waves 1 .. kSweepWaves - 1: greedy, largest row (r + 1
+// tiles) first, to the least loaded wave.
 __host__ __device__ constexpr int sweep_row_owner(int R, int r) {
-  int load[3] = {0, 0, 0}, owner = 0;
+  int load[kSweepWaves - 1] = {}, owner = 0;
   for (int row = R - 1; row >= 0; --row) {
     int w = 0;
-    for (int k = 1; k < 3; ++k)
+    for (int k = 1; k < kSweepWaves - 1; ++k)
       if (load[k] < load[w]) w = k;
     load[w] += row + 1;
     if (row == r) owner = w + 1;
@@ -493,6 +495,22 @@ __device__ __forceinline__ bool sweep_update_role(const SweepLds& L, const doubl
   return ok;
 }
 
+// Update wave `wave` (W .. kSweepWaves - 1) takes its role with its tiles as
+// compile-time constants.
+template <int R, int W, typename TO>
+__device__ __forceinline__ bool sweep_update_dispatch(int wave, const SweepLds& L,
+                                                      const double* __restrict__ M, int P,
+                                                      int npiv, bool solve_only, int lane,
+                                                      TO* __restrict__ inv_out, int64_t ldo,
+                                                      TO* __restrict__ dir_out, double* ydir) {
+  if constexpr (W + 1 < kSweepWaves) {
+    if (wave != W)
+      return sweep_update_dispatch<R, W + 1, TO>(wave, L, M, P, npiv, solve_only, lane, inv_out,
+                                                 ldo, dir_out, ydir);
+  }
+  return sweep_update_role<R, W, TO>(L, M, P, npiv, solve_only, lane, inv_out, ldo, dir_out, ydir);
+}
+
 // With post != nullptr (direction mode only) the direction y = -H^{-1} g is
 // multiplied by the symmetric npiv x npiv matrix `post` (row-major, leading
 // dimension ldp) before it is written: dir_out = post y.
@@ -527,12 +545,9 @@ __device__ __forceinline__ void sweep_matrix(
   if (wave == 0)
     ok = sweep_pivot_role<R>(L, npiv, lane, postmul ? post : nullptr,
                              static_cast<int64_t>(npiv) * ldp * 8, warm_acc);
-  else if (wave == 1)
-    ok = sweep_update_role<R, 1, TO>(L, M, P, npiv, solve_only, lane, inv, ldo, dir_out, yd);
-  else if (wave == 2)
-    ok = sweep_update_role<R, 2, TO>(L, M, P, npiv, solve_only, lane, inv, ldo, dir_out, yd);
   else
-    ok = sweep_update_role<R, 3, TO>(L, M, P, npiv, solve_only, lane, inv, ldo, dir_out, yd);
+    ok = sweep_update_dispatch<R, 1, TO>(wave, L, M, P, npiv, solve_only, lane, inv, ldo, dir_out,
+                                         yd);
   if (postmul) {
     // dir_out[i] = sum_j post[j][i] y_j (post is symmetric): thread t owns
     // output i = t % kOut for the columns j = h, h + kGroups, ... with
@@ -585,7 +600,7 @@ __device__ __forceinline__ void sweep_matrix(
 }
 
 template <int R, typename TO>
-__global__ void __launch_bounds__(kSweepTD * kSweepTD) sweep_kernel(
+__global__ void __launch_bounds__(kSweepThreads) sweep_kernel(
     const double* __restrict__ M, int P, int npiv, int mode, TO* __restrict__ inv_out, int64_t ldo,
     TO* __restrict__ dir_out, int32_t* status, int fail_code, const double* __restrict__ post,
     int64_t ldp) {
@@ -596,7 +611,7 @@ __global__ void __launch_bounds__(kSweepTD * kSweepTD) sweep_kernel(
 // G), MODE 1 solves (S^T S + lambda G^2) y = -S^T r0 from Hsum and writes the
 // GGN direction dU = G y (status word 1).  One item per instance.
 template <int R, int MODE>
-__global__ void __launch_bounds__(kSweepTD * kSweepTD) batch_sweep_kernel(
+__global__ void __launch_bounds__(kSweepThreads) batch_sweep_kernel(
     const BatchInst* __restrict__ inst, BatchLaunch L) {
   for (int w = blockIdx.x; w < L.count; w += gridDim.x) {
     const BatchInst& b = inst[L.items[w].inst];

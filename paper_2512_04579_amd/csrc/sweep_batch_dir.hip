@@ -8,7 +8,7 @@ hipError_t launch_batch_sweep_mode1(int R, const BatchInst* inst, const BatchLau
                                      hipStream_t st) {
 #define GNM_BS_CASE(RR)                                                                        \
   case RR:                                                                                     \
-    hipLaunchKernelGGL((batch_sweep_kernel<RR, 1>), dim3(L.blocks), dim3(kSweepTD * kSweepTD), \
+    hipLaunchKernelGGL((batch_sweep_kernel<RR, 1>), dim3(L.blocks), dim3(kSweepThreads), \
                        0, st, inst, L);                                                        \
     break;
   switch (R) {

@@ -1,5 +1,5 @@
-// Single-instance sweep launcher, float output: one workgroup of 4 waves,
-// R = ceil(P / 16) <= 13 for P <= 208.
+// Single-instance sweep launcher, float output: one workgroup of kSweepWaves
+// waves, R = ceil(P / 16) <= 13 for P <= 208.
 #include "sweep.hpp"
 
 namespace gnm {
@@ -10,7 +10,7 @@ hipError_t launch_sweep(int P, int npiv, int mode, const double* M, float* inv_o
   const int R = (P + kSweepTD - 1) / kSweepTD;
 #define GNM_SWEEP_CASE(RR)                                                                        \
   case RR:                                                                                        \
-    hipLaunchKernelGGL((sweep_kernel<RR, float>), dim3(1), dim3(kSweepTD * kSweepTD), 0, st, M, P, \
+    hipLaunchKernelGGL((sweep_kernel<RR, float>), dim3(1), dim3(kSweepThreads), 0, st, M, P, \
                        npiv, mode, inv_out, ldo, dir_out, status, fail_code, post, ldp);          \
     break;
   switch (R) {
