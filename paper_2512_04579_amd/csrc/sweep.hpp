@@ -247,6 +247,29 @@ __device__ __forceinline__ f64x4 mfma_abt16(const double* __restrict__ pa,
   return acc;
 }
 
+// -Y^T = -(D^{-1} Z^T) for one row tile (Z = 16 panel rows, D^{-1}
+// symmetric) in the accumulator layout: element e of lane l is
+// -Y[l % 16][4 e + l / 16].
+__device__ __forceinline__ f64x4 sweep_neg_yt(const double* __restrict__ zrows,
+                                              const double* __restrict__ dinv, int lane) {
+  const f64x4 y = mfma_abt16(dinv, zrows, f64x4{0, 0, 0, 0}, lane);
+  return f64x4{-y[0], -y[1], -y[2], -y[3]};
+}
+
+// acc - Y Z^T for one tile with -Y^T from sweep_neg_yt: step e takes
+// k = 4 e + l / 16, its A operand straight from the registers and its B
+// operand Z[l % 16][k] from the 16 rows of pb, so Y never goes through LDS.
+__device__ __forceinline__ f64x4 mfma_nyt_zt(const f64x4 nyt, const double* __restrict__ pb,
+                                             f64x4 acc, int lane) {
+  const double* b = pb + (lane & 15) * kSweepLd + (lane >> 4);
+  const double b0 = b[0], b1 = b[4], b2 = b[8], b3 = b[12];
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(nyt[0], b0, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(nyt[1], b1, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(nyt[2], b2, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(nyt[3], b3, acc, 0, 0, 0);
+  return acc;
+}
+
 // -Y = -(Z D^{-1}) for one row tile (Z = 16 panel rows) into 16 rows of `dst`.
 __device__ __forceinline__ void sweep_neg_y(const double* __restrict__ zrows,
                                             const double* __restrict__ dinv,
@@ -264,7 +287,6 @@ struct SweepLds {
   double* dinv;   // 2 x 16 rows
   double* dtin;   // 2 diagonal tiles handed to wave 0
   double* dtout;  // 2 swept diagonal tiles handed back
-  double* ysc;    // wave 0's scratch rows
   double* wmax;
   int* diag_ok;  // 2, by block parity
   int pan_stride;
@@ -300,10 +322,9 @@ __device__ __forceinline__ bool sweep_pivot_role(const SweepLds& L, int npiv, in
 #pragma unroll
       for (int e = 0; e < 4; ++e) d[e] = L.dtin[(b & 1) * TL + (4 * e + q) * LD + li];
       if (b > 0) {
+        // block b - 1 applied with its Y^T kept in registers
         const double* zb = L.pan + ((b - 1) & 1) * L.pan_stride + 16 * b * LD;
-        sweep_neg_y(zb, L.dinv + ((b - 1) & 1) * TL, L.ysc, lane);
-        wave_lds_sync();
-        d = mfma_abt16(L.ysc, zb, d, lane);
+        d = mfma_nyt_zt(sweep_neg_yt(zb, L.dinv + ((b - 1) & 1) * TL, lane), zb, d, lane);
       }
       // panel rows of block b: -I for the pivots, the tile itself otherwise
       double* pb = L.pan + (b & 1) * L.pan_stride + 16 * b * LD;
@@ -523,7 +544,7 @@ __device__ __forceinline__ void sweep_matrix(
   __shared__ __attribute__((aligned(16))) double pan[2 * 16 * R * LD];
   __shared__ __attribute__((aligned(16))) double ybufw[16 * R * LD];
   __shared__ __attribute__((aligned(16))) double ybufp[16 * R * LD];
-  __shared__ __attribute__((aligned(16))) double tiles16[7 * TL];
+  __shared__ __attribute__((aligned(16))) double tiles16[6 * TL];
   __shared__ double wmax[kSweepWaves];
   __shared__ int diag_ok[2];
   // y with zero padding up to the last index the post-multiplication reads
@@ -531,7 +552,7 @@ __device__ __forceinline__ void sweep_matrix(
   __shared__ double ydir[kYdir];
   __shared__ double ypart[kSweepWaves * kWave > 16 * R ? kSweepWaves * kWave : 16 * R];
   const SweepLds L{pan,           ybufw,          ybufp,    tiles16,  tiles16 + 2 * TL,
-                   tiles16 + 4 * TL, tiles16 + 6 * TL, wmax, diag_ok, 16 * R * LD};
+                   tiles16 + 4 * TL, wmax, diag_ok, 16 * R * LD};
   const int lane = threadIdx.x & (kWave - 1);
   // the wave index is uniform: readfirstlane lets each wave take its role
   // (and its tiles) as a scalar branch
