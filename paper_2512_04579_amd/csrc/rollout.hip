@@ -653,17 +653,28 @@ __device__ __forceinline__ T di_rollout(int N, T dt, const T* __restrict__ x0,
   }
   const T hdt2 = T(0.5) * dt * dt;
   T cost = 0;
-  for (int k = 0; k < N; ++k) {
+  if (N <= 0) return cost;
+  // The raw control loads of a step are issued kAhead steps before it runs,
+  // from indices clamped to the last step (unconditional, so no load sits in
+  // a branch): the compiler cannot move a step's loads above the previous
+  // step's residual stores, and without the ring every step would wait for
+  // its own loads.  Whole turns of the ring run first; the last N % kAhead
+  // steps then find their controls in the ring already.  The step's fused
+  // multiply-adds are written out and no others are formed, so the storing
+  // and the cost-only instantiations (the rollout's nominal and the line
+  // search's chosen candidate) round alike.
+  constexpr int kAhead = 8;
+  auto step = [&](int k, const T (&u)[D]) {
+#pragma clang fp contract(off)
     const int64_t base = static_cast<int64_t>(k) * 3 * D;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      const T u = ctrl(k * D + j);
-      p[j] = p[j] + dt * v[j] + hdt2 * u;
-      v[j] = v[j] + dt * u;
+      p[j] = fma(hdt2, u[j], fma(dt, v[j], p[j]));
+      v[j] = fma(dt, u[j], v[j]);
       const T e0 = wp[j] * (p[j] - rp[j]);
       const T e1 = wv[j] * (v[j] - rv[j]);
-      const T e2 = wu[j] * u;
-      cost += e0 * e0 + e1 * e1 + e2 * e2;
+      const T e2 = wu[j] * u[j];
+      cost += fma(e2, e2, fma(e1, e1, e0 * e0));
       if constexpr (STORE) {
         if (store_ok) {
           R[(base + j) * ldr + col] = e0;
@@ -671,6 +682,35 @@ __device__ __forceinline__ T di_rollout(int N, T dt, const T* __restrict__ x0,
           R[(base + 2 * D + j) * ldr + col] = e2;
         }
       }
+    }
+  };
+  T la[kAhead][D], lb[kAhead][D];
+#pragma unroll
+  for (int s = 0; s < kAhead; ++s)
+#pragma unroll
+    for (int j = 0; j < D; ++j) ctrl.load(min(s, N - 1) * D + j, la[s][j], lb[s][j]);
+  const int nfull = N - N % kAhead;
+  for (int k0 = 0; k0 < nfull; k0 += kAhead) {
+#pragma unroll
+    for (int s = 0; s < kAhead; ++s) {
+      const int kn = min(k0 + s + kAhead, N - 1);
+      T u[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        u[j] = ctrl.value(la[s][j], lb[s][j]);
+        ctrl.load(kn * D + j, la[s][j], lb[s][j]);
+      }
+      step(k0 + s, u);
+    }
+  }
+  // ring slot s now holds step nfull + s
+#pragma unroll
+  for (int s = 0; s < kAhead; ++s) {
+    if (nfull + s < N) {  // uniform
+      T u[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) u[j] = ctrl.value(la[s][j], lb[s][j]);
+      step(nfull + s, u);
     }
   }
   return T(0.5) * cost;
