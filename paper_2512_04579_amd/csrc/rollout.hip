@@ -314,7 +314,7 @@ constexpr int staged_flush_steps() {
 // cost 1/2 ||r||^2 (identical in every lane of the group; 0 without COST,
 // which skips the cost terms).  All lanes of the wave must call this
 // together (the DPP shifts read neighbouring lanes).
-template <typename T, int G, bool COST, class Ctrl, class Sink>
+template <typename T, int G, bool COST, bool AHEAD = false, class Ctrl, class Sink>
 __device__ __forceinline__ T chain_rollout(const ChainDev<T>& cd, int N,
                                            const T* __restrict__ x0, const T* __restrict__ q,
                                            const T* __restrict__ r, const T* __restrict__ xref,
@@ -343,11 +343,22 @@ __device__ __forceinline__ T chain_rollout(const ChainDev<T>& cd, int N,
   const T h_im = h * im, hh_im = hh * im, h6_im = h6 * im;
   T cost = 0;
   for (int k0 = 0; k0 < N; k0 += 4) {
+    // AHEAD: the controls of the group's four steps are read at its top
+    // (indices clamped to the last step), so their loads wait once per group
+    T uu[4][2];
+    if constexpr (AHEAD) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int kk = min(k0 + t, N - 1);
+        uu[t][0] = ctrl(2 * kk);
+        uu[t][1] = ctrl(2 * kk + 1);
+      }
+    }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int k = k0 + t;
       if (k >= N) break;  // uniform: every lane has the same horizon
-      const T u0 = ctrl(2 * k), u1 = ctrl(2 * k + 1);
+      const T u0 = AHEAD ? uu[t][0] : ctrl(2 * k), u1 = AHEAD ? uu[t][1] : ctrl(2 * k + 1);
       if (!free_mass) {  // the end mass moves with the commanded velocity
         vx = u0;
         vy = u1;
@@ -821,9 +832,9 @@ __device__ __forceinline__ void line_search_chain_block(
   // groups past the last candidate repeat it and store nothing
   VectorSink<T> vsink{Rc != nullptr && j < L ? Rc + j * m : nullptr, cd.M};
   auto roll = [&](const auto& ctrl) {
-    if (Rc != nullptr) return chain_rollout<T, G, true>(cd, N, x0, q, r, xref, ctrl, vsink);
+    if (Rc != nullptr) return chain_rollout<T, G, true, true>(cd, N, x0, q, r, xref, ctrl, vsink);
     NoSink sink;
-    return chain_rollout<T, G, true>(cd, N, x0, q, r, xref, ctrl, sink);
+    return chain_rollout<T, G, true, true>(cd, N, x0, q, r, xref, ctrl, sink);
   };
   T c;
   if (stage_ctl) {
