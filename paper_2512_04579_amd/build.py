@@ -22,8 +22,8 @@ ARCH = "gfx950"
 # Longest compiles first (the sweep units instantiate one kernel per 16-row
 # class), so the parallel build ends with the short ones.
 SOURCES = ["sweep_batch_inv.hip", "sweep_batch_dir.hip", "sweep_f32.hip", "sweep_f64.hip",
-           "fused.hip", "dense.hip", "gemm.hip", "rollout.hip", "abi.cpp", "batch.cpp", "sample.hip", "mppi.hip",
-           "mlp.hip"]
+           "fused.hip", "dense.hip", "gemm.hip", "gemm_plain.hip", "rollout.hip", "abi.cpp",
+           "batch.cpp", "sample.hip", "mppi.hip", "mlp.hip"]
 
 # Packed FP32 VALU ops are switched off for every HIP translation unit.
 HIPCC_FLAGS = [
@@ -36,10 +36,12 @@ HIPCC_FLAGS = [
 # The sweep units keep their f64 MFMA accumulators in ordinary VGPRs: the
 # update waves select between tiles and zero pivot rows in place, which with
 # accumulators in AGPRs costs a copy out and back for every tile (measured: the
-# sweep 11 % faster, no spills).
+# sweep 11 % faster, no spills).  So does the plain-BF16 contraction unit
+# (measured 0.8 % faster for the whole c4 iteration), while the BF16x3
+# contraction keeps AGPRs (with VGPRs c2 was no faster).
 EXTRA_FLAGS = {src: ["-mllvm", "-amdgpu-mfma-vgpr-form"]
                for src in ("sweep_batch_inv.hip", "sweep_batch_dir.hip", "sweep_f32.hip",
-                           "sweep_f64.hip")}
+                           "sweep_f64.hip", "gemm_plain.hip")}
 
 
 def _hipcc() -> str:

@@ -624,6 +624,18 @@ hipError_t bf16_dispatch(int nt, dim3 grid, hipStream_t st, int m, int n, int K,
 
 }  // namespace
 
+#ifdef GNM_GEMM_PLAIN_UNIT
+// The plain-BF16 contraction (one product per term), from its own unit.
+hipError_t launch_contract_bf16_plain(int nt, dim3 grid, hipStream_t st, int m, int n, int K,
+                                      const float* R, int64_t ldr, const float* r0, const float* W,
+                                      int64_t ldw, int split_len, float* part, int npad,
+                                      int arows, bool vec) {
+  return vec ? bf16_dispatch<1, true>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, split_len, part,
+                                      npad, arows)
+             : bf16_dispatch<1, false>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, split_len, part,
+                                       npad, arows);
+}
+#else
 int contract_kw(size_t elem_size, int ncol) {
   const int nt = (ncol + 15) / 16;
   // the split epilogue parks 4 waves' tiles in LDS: stay within 64 KB
@@ -701,10 +713,9 @@ hipError_t launch_contract_bf16(int terms, int m, int n, int K, const float* R, 
                                         npad, arows)
                : bf16_dispatch<3, false>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, split_len, part,
                                          npad, arows);
-  return vec ? bf16_dispatch<1, true>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, split_len, part,
-                                      npad, arows)
-             : bf16_dispatch<1, false>(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, split_len, part,
-                                       npad, arows);
+  return launch_contract_bf16_plain(nt, grid, st, m, n, K, R, ldr, r0, W, ldw, split_len, part,
+                                    npad, arows, vec);
 }
+#endif  // GNM_GEMM_PLAIN_UNIT
 
 }  // namespace gnm

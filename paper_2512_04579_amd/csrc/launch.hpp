@@ -92,6 +92,11 @@ hipError_t launch_contract_bf16(int terms, int m, int n, int K, const float* R, 
                                 const float* r0, const float* W, int64_t ldw, int nsplit,
                                 int split_len, float* part, int npad, hipStream_t st,
                                 bool with_gram = false);
+// The terms == 1 path of launch_contract_bf16 (defined in gemm_plain.hip).
+hipError_t launch_contract_bf16_plain(int nt, dim3 grid, hipStream_t st, int m, int n, int K,
+                                      const float* R, int64_t ldr, const float* r0, const float* W,
+                                      int64_t ldw, int split_len, float* part, int npad,
+                                      int arows, bool vec);
 
 // Symmetric sweep of an SPD matrix M (P x P, full, double) over its first
 // npiv pivots (sweep.hpp): kSweepInverse writes the inverse of the leading
